@@ -1,0 +1,104 @@
+"""3D real-to-complex / complex-to-real transforms in FP64 (oracle; test infrastructure).
+
+Conventions follow the paper's Section "Fast Fourier Transform": the inverse
+transform is the plain sum over the Fourier basis exp(+i k.x) with no 1/N, so the
+1/N^3 sits on the forward transform.  Layout: real [nx][ny][nz], complex
+[nx][ny][nz/2+1] (Appendix A's n0 x n1 x (n2/2+1)); wavenumbers on x and y are
+0..N/2-1 followed by -N/2..-1, and kz = 0..N/2 is stored.
+
+The transforms themselves are in ``fftref.c`` (own recursive mixed-radix FFT).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_rfft3.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_irfft3.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_fft1d.argtypes = [dp, ctypes.c_int, ctypes.c_int]
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def fft1d(x, sign=-1):
+    """Unscaled 1D DFT of a complex vector: sum_j x_j exp(sign 2 pi i j k / n)."""
+    a = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    rc = lib().orc_fft1d(_dp(a.view(np.float64)), a.shape[0], int(sign))
+    if rc != 0:
+        raise ValueError("orc_fft1d failed")
+    return a
+
+
+def rfft3(f):
+    """Forward transform F(k) = N^-3 sum_x f(x) exp(-i k.x) of a real [..., nx, ny, nz] array."""
+    f = np.asarray(f)
+    lead = f.shape[:-3]
+    nx, ny, nz = f.shape[-3:]
+    src = np.ascontiguousarray(f, dtype=np.float64).reshape((-1, nx, ny, nz))
+    out = np.empty((src.shape[0], nx, ny, nz // 2 + 1), dtype=np.complex128)
+    for b in range(src.shape[0]):
+        s = np.ascontiguousarray(src[b])
+        o = out[b]
+        rc = lib().orc_rfft3(_dp(s), _dp(o.view(np.float64)), nx, ny, nz)
+        if rc != 0:
+            raise ValueError("orc_rfft3: unsupported shape %r" % (f.shape,))
+    return out.reshape(lead + (nx, ny, nz // 2 + 1))
+
+
+def irfft3(F, nz=None):
+    """Inverse transform f(x) = sum_{kz} w(kz) Re[sum_{kx,ky} F(k) exp(i k.x)] (unscaled)."""
+    F = np.asarray(F)
+    lead = F.shape[:-3]
+    nx, ny, nzh = F.shape[-3:]
+    if nz is None:
+        nz = 2 * (nzh - 1)
+    src = np.ascontiguousarray(F, dtype=np.complex128).reshape((-1, nx, ny, nzh))
+    out = np.empty((src.shape[0], nx, ny, nz), dtype=np.float64)
+    for b in range(src.shape[0]):
+        s = np.ascontiguousarray(src[b])
+        o = out[b]
+        rc = lib().orc_irfft3(_dp(s.view(np.float64)), _dp(o), nx, ny, nz)
+        if rc != 0:
+            raise ValueError("orc_irfft3: unsupported shape %r" % (F.shape,))
+    return out.reshape(lead + (nx, ny, nz))
+
+
+def wavenumbers(n):
+    """Integer wavenumbers (kx, ky, kz) broadcastable to [n][n][n/2+1].
+
+    x and y: i for i < n/2, else i - n (the Nyquist index n/2 maps to -n/2);
+    z: 0..n/2.
+    """
+    k = np.arange(n)
+    k = np.where(k < n // 2, k, k - n)
+    kz = np.arange(n // 2 + 1)
+    return k[:, None, None], k[None, :, None], kz[None, None, :]
+
+
+def hermitian_weight(n):
+    """w(kz): 1 on the kz = 0 and kz = n/2 planes, 2 elsewhere (each stored mode
+    with 0 < kz < n/2 stands for itself and its conjugate)."""
+    w = np.full(n // 2 + 1, 2.0)
+    w[0] = 1.0
+    w[n // 2] = 1.0
+    return w[None, None, :]
