@@ -1,0 +1,160 @@
+/*
+ * tk.h -- C ABI of libtk, an MI355X (gfx950) implementation of the FFTK/Tarang hot path:
+ * the 3D real-to-complex / complex-to-real FFT and the pseudo-spectral Navier-Stokes
+ * step built on it (Chatterjee et al., "Scaling of a Fast Fourier Transform and a
+ * Pseudo-spectral Fluid Solver up to 196608 cores").
+ *
+ * General conventions
+ *  - Every data pointer is a DEVICE pointer owned by the caller, unless stated.  Handles
+ *    own their internal tables and scratch memory.  Nothing is freed behind the caller.
+ *  - Streams are hipStream_t values passed as void*; NULL is the default stream.  Calls
+ *    are asynchronous on the stream unless documented as synchronising.
+ *  - Every call returns a tk_status; no exception crosses the ABI.  On a non-OK status,
+ *    tk_last_error() returns a thread-local message, and no partial work was queued
+ *    unless the status is TK_EHIP (a launch failure).
+ *  - Calls on one handle must not overlap in time from several host threads.
+ *  - Real fields are C-order [nx][ny][nz] (z fastest); spectral fields are C-order
+ *    [nx][ny][nz/2+1] complex, interleaved (re, im): the n0 x n1 x (n2/2+1) layout of the
+ *    paper's Appendix A.  Wavenumbers along x and y are 0..n/2-1, -n/2..-1; kz = 0..nz/2.
+ *  - Supported line lengths: n = 2^a or 3 * 2^a with 8 <= n <= 1024 (the paper's XC40
+ *    grids are 3 * 2^n; Section "Scaling on Cray XC40").  Others give TK_EUNSUPPORTED.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TK_OK = 0,
+    TK_EINVAL = -1,        /* bad argument (null pointer, negative count, ...) */
+    TK_EUNSUPPORTED = -2,  /* valid request this library does not implement (size, dtype) */
+    TK_ENOMEM = -3,        /* device or host allocation failed */
+    TK_EHIP = -4,          /* a HIP call or kernel launch failed */
+    TK_ESTATE = -5         /* handle in the wrong state, or non-finite diagnostics */
+} tk_status;
+
+typedef enum { TK_F32 = 0, TK_F64 = 1 } tk_dtype;
+
+typedef struct tk_fft3d_s *tk_fft3d_t;
+typedef struct tk_ns_s *tk_ns_t;
+typedef struct tk_nsb_s *tk_nsb_t;
+
+/* Thread-local text describing the last non-OK status of this thread ("" if none). */
+const char *tk_last_error(void);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int tk_version(void);
+
+/* ------------------------------------------------------------------------------------
+ * 3D FFT in the Fourier (FFF) basis.
+ * Paper, Section "Fast Fourier Transform": the inverse transform is the plain sum
+ *   f(x) = sum_k F(k) exp(+i k.x),
+ * so the forward transform carries the 1/(nx ny nz) factor:
+ *   F(k) = (nx ny nz)^-1 sum_x f(x) exp(-i k.x).
+ * Section "Parallelization Strategy": forward = Z r2c, then Y c2c, then X c2c; the
+ * inverse is the reverse.  On one GPU the two all-to-all exchanges of the pencil
+ * algorithm disappear and, as in the transpose-free scheme of Appendix A, the axes
+ * are never permuted: the Y and X passes read strided columns through LDS tiles.
+ * ------------------------------------------------------------------------------------ */
+
+/* Flags for fft3d_plan_create. */
+#define TK_FFT_TIMING 0x1u    /* record per-pass HIP events (fft3d_pass_times) */
+#define TK_FFT_NO_TUNE 0x2u   /* ignore the autotuner cache, use default tiles */
+
+/* Create a plan for `batch` fields of nx*ny*nz points in dtype dt.  Allocates twiddle
+ * tables (a few KB) on the current device.  Sizes must be supported (see above);
+ * batch >= 1.  Returns TK_EUNSUPPORTED for unsupported sizes, TK_EINVAL for null. */
+tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
+                            unsigned flags);
+
+/* Bytes of device workspace fft3d_c2r needs (one spectral field per batch member). */
+tk_status fft3d_workspace_size(tk_fft3d_t plan, size_t *bytes);
+
+/* Supply caller-owned device workspace of at least fft3d_workspace_size bytes (NULL
+ * returns to plan-owned workspace, allocated lazily on the first c2r).  The caller must
+ * keep it alive while the plan uses it. */
+tk_status fft3d_set_workspace(tk_fft3d_t plan, void *dev_ptr);
+
+/* Forward r2c: real_in [batch][nx][ny][nz] -> cplx_out [batch][nx][ny][nz/2+1],
+ * scaled by 1/(nx ny nz).  real_in is not modified.  The buffers must not overlap. */
+tk_status fft3d_r2c(tk_fft3d_t plan, const void *real_in, void *cplx_out, void *stream);
+
+/* Inverse c2r, unscaled: cplx_in -> real_out.  cplx_in is preserved (the solver needs
+ * its spectral state intact).  On the kz = 0 and kz = nz/2 planes only the Hermitian
+ * part matters: the result is sum_{kz} w(kz) Re[sum_{kx,ky} F(k) exp(i k.x)] with
+ * w = 1 on those planes and 2 elsewhere. */
+tk_status fft3d_c2r(tk_fft3d_t plan, const void *cplx_in, void *real_out, void *stream);
+
+/* Parseval sums in FP64: out[0] = sum f^2 / (nx ny nz) over the real field (batch
+ * member 0), out[1] = sum w(kz) |F|^2 over its half spectrum.  Synchronises stream. */
+tk_status fft3d_parseval(tk_fft3d_t plan, const void *real, const void *cplx, double out[2],
+                         void *stream);
+
+/* Per-pass durations in ms of the last r2c (t[0..2] = Z, Y, X) and c2r (t[3..5] = X, Y,
+ * Z), for a plan created with TK_FFT_TIMING.  Synchronises. */
+tk_status fft3d_pass_times(tk_fft3d_t plan, float t[6]);
+
+/* Describe the tile configuration the plan uses for pass p (0 = Z, 1 = Y, 2 = X) as
+ * text in buf (NUL-terminated, at most len bytes). */
+tk_status fft3d_describe(tk_fft3d_t plan, int pass, char *buf, int len);
+
+tk_status fft3d_plan_destroy(tk_fft3d_t plan);
+
+/* ------------------------------------------------------------------------------------
+ * Pseudo-spectral incompressible Navier-Stokes in the periodic (2 pi)^3 box.
+ * Paper, Section "Spectral Solver": the Fourier-space momentum equation (eq:NSk) with
+ * the constraint k . u^ = 0 (eq:continuity2); nonlinear term pseudo-spectral (to real
+ * space, multiply, back), dealiased by the 2/3 rule.  Nine 3D transforms per
+ * right-hand side: six inverse (u, omega), three forward (u x omega).
+ * State: u^ [3][n][n][n/2+1] complex in dtype, zero outside the 2/3 set and solenoidal.
+ * ------------------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;            /* grid points per axis (supported length, see above) */
+    tk_dtype dtype;   /* TK_F32 or TK_F64 */
+    double nu;        /* kinematic viscosity */
+    double cfl;       /* > 0: ns_step ignores dt and uses h = cfl (2 pi / n) / max(|ux|+|uy|+|uz|) */
+    int scheme;       /* 0: integrating-factor RK2 (Heun); 1: integrating-factor RK4 */
+    unsigned flags;   /* reserved, 0 */
+} ns_config;
+
+/* Create a solver; allocates its workspace (about 12 spectral fields). */
+tk_status ns_create(tk_ns_t *ns, const ns_config *cfg);
+
+/* N(u^) = P M F[u x omega] for state uhat (viscous term excluded): rhs_out has the
+ * state's layout.  uhat is not modified. */
+tk_status ns_rhs(tk_ns_t ns, const void *uhat, void *rhs_out, void *stream);
+
+/* Advance uhat in place by nsteps steps.  With cfg.cfl > 0 the step size is computed on
+ * the device each step (dt is ignored); else h = dt.  *t_inout (host) is advanced by the
+ * elapsed time; this synchronises the stream at the end of the call. */
+tk_status ns_step(tk_ns_t ns, void *uhat_inout, double dt, int nsteps, double *t_inout,
+                  void *stream);
+
+/* FP64 diagnostics of state uhat: energy E = sum w 1/2|u^|^2, dissipation 2 nu sum w
+ * 1/2 |k|^2 |u^|^2, shell spectrum E(s) for s < nshell (shell s: (2s-1)^2 <= 4|k|^2 <
+ * (2s+1)^2; any pointer may be NULL), and max |k.u^|/(|k||u^|).  Synchronises stream.
+ * Returns TK_ESTATE if the energy is not finite. */
+tk_status ns_diagnostics(tk_ns_t ns, const void *uhat, double *energy, double *dissipation,
+                         double *spectrum, int nshell, double *max_div, void *stream);
+
+/* Initial state from real Gaussian noise [3][n][n][n] (dtype of the solver): r2c,
+ * projection, 2/3 mask, k = 0 removed, each shell s >= 1 rescaled to s^4 exp(-2(s/4)^2),
+ * total energy set to `energy`.  Synchronises stream. */
+tk_status ns_init_random(tk_ns_t ns, const void *noise, void *uhat_out, double energy,
+                         void *stream);
+
+/* Last step size used by ns_step (host value; synchronises nothing). */
+tk_status ns_last_dt(tk_ns_t ns, double *dt);
+
+tk_status ns_destroy(tk_ns_t ns);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TK_H */

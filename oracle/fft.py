@@ -102,3 +102,41 @@ def hermitian_weight(n):
     w[0] = 1.0
     w[n // 2] = 1.0
     return w[None, None, :]
+
+
+def dft_at(f, ks):
+    """The forward transform's definition evaluated at selected modes only:
+    F(k) = N^-3 sum_x f(x) exp(-i k.x) for each (kx_idx, ky_idx, kz) in ks.  Cost O(N^3)
+    per distinct kz plus O(N^2) per mode: used to check outputs of grids too large for
+    the full oracle transform."""
+    f = np.asarray(f)
+    nx, ny, nz = f.shape
+    ks = [tuple(int(v) for v in k) for k in ks]
+    kzs = sorted(set(k[2] for k in ks))
+    ez = np.exp(-2j * np.pi * np.outer(np.arange(nz), kzs) / nz)            # [nz][K]
+    g = (f.reshape(nx * ny, nz).astype(np.float64) @ ez).reshape(nx, ny, len(kzs))
+    out = []
+    for (a, b, c) in ks:
+        ex = np.exp(-2j * np.pi * a * np.arange(nx) / nx)
+        ey = np.exp(-2j * np.pi * b * np.arange(ny) / ny)
+        out.append(ex @ g[:, :, kzs.index(c)] @ ey)
+    return np.array(out) / (nx * ny * nz)
+
+
+def idft_at(F, nz, xs):
+    """The inverse transform's definition at selected grid points (ix, iy, iz):
+    f(x) = sum_{kz} w(kz) Re[sum_{kx,ky} F(k) exp(i k.x)]."""
+    F = np.asarray(F)
+    nx, ny, nzh = F.shape
+    w = np.full(nzh, 2.0)
+    w[0] = 1.0
+    w[nz // 2] = 1.0
+    out = []
+    for (a, b, c) in xs:
+        ex = np.exp(2j * np.pi * a * np.arange(nx) / nx)
+        ey = np.exp(2j * np.pi * b * np.arange(ny) / ny)
+        ez = np.exp(2j * np.pi * c * np.arange(nzh) / nz)
+        g = np.tensordot(ex, F, axes=(0, 0))          # [ny][nzh]
+        g = ey @ g                                     # [nzh]
+        out.append(np.sum(w * np.real(g * ez)))
+    return np.array(out)

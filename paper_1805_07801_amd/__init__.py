@@ -1,0 +1,163 @@
+"""Python binding of libtk (MI355X / gfx950): argument marshalling over the C ABI in
+include/tk.h.  Every step of the computation runs in libtk's HIP kernels; PyTorch only
+provides device memory and streams.  There is no CPU fallback: if libtk.so is missing
+or cannot be loaded, every call raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtk.so")
+
+TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ESTATE = 0, -1, -2, -3, -4, -5
+TK_F32, TK_F64 = 0, 1
+TK_FFT_TIMING, TK_FFT_NO_TUNE = 0x1, 0x2
+
+_lib = None
+
+
+class TkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tk status %d: %s" % (status, msg))
+        self.status = status
+
+
+def _declare(L):
+    vp, i, u, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    sigs = {
+        "tk_last_error": ([], ctypes.c_char_p),
+        "tk_version": ([], i),
+        "fft3d_plan_create": ([P(vp), i, i, i, i, i, u], i),
+        "fft3d_workspace_size": ([vp, P(sz)], i),
+        "fft3d_set_workspace": ([vp, vp], i),
+        "fft3d_r2c": ([vp, vp, vp, vp], i),
+        "fft3d_c2r": ([vp, vp, vp, vp], i),
+        "fft3d_parseval": ([vp, vp, vp, P(d), vp], i),
+        "fft3d_pass_times": ([vp, P(ctypes.c_float)], i),
+        "fft3d_describe": ([vp, i, ctypes.c_char_p, i], i),
+        "fft3d_plan_destroy": ([vp], i),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+def load(path=None):
+    """Load libtk.so (built in-tree by build.py); raises if it is not there."""
+    global _lib
+    if _lib is None:
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise TkError(TK_ESTATE, "libtk.so not built (%s); run paper_1805_07801_amd/build.py" % p)
+        _lib = _declare(ctypes.CDLL(p))
+    return _lib
+
+
+def lib():
+    return load()
+
+
+def check(status):
+    if status != TK_OK:
+        raise TkError(status, lib().tk_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dtype_code(dtype):
+    import torch
+    if dtype in (torch.float32, torch.complex64):
+        return TK_F32
+    if dtype in (torch.float64, torch.complex128):
+        return TK_F64
+    raise TkError(TK_EUNSUPPORTED, "dtype %s" % dtype)
+
+
+class FFT3D:
+    """Plan for batched 3D r2c / c2r transforms of [batch][nx][ny][nz] real fields."""
+
+    def __init__(self, nx, ny=None, nz=None, batch=1, dtype=None, flags=0):
+        import torch
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        dtype = dtype or torch.float32
+        self.shape = (nx, ny, nz)
+        self.batch = batch
+        self.dtype = dtype
+        self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
+        h = ctypes.c_void_p()
+        check(lib().fft3d_plan_create(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), flags))
+        self.h = h
+
+    def _check_real(self, t):
+        nx, ny, nz = self.shape
+        if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != self.batch * nx * ny * nz:
+            raise TkError(TK_EINVAL, "real tensor must be contiguous %s on GPU with %d elements"
+                          % (self.dtype, self.batch * nx * ny * nz))
+
+    def _check_cplx(self, t):
+        nx, ny, nz = self.shape
+        n = self.batch * nx * ny * (nz // 2 + 1)
+        if t.dtype != self.cdtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise TkError(TK_EINVAL, "complex tensor must be contiguous %s on GPU with %d elements" % (self.cdtype, n))
+
+    def empty_cplx(self):
+        import torch
+        nx, ny, nz = self.shape
+        return torch.empty((self.batch, nx, ny, nz // 2 + 1), dtype=self.cdtype, device="cuda")
+
+    def empty_real(self):
+        import torch
+        return torch.empty((self.batch,) + self.shape, dtype=self.dtype, device="cuda")
+
+    def r2c(self, real, out=None, stream=None):
+        self._check_real(real)
+        out = self.empty_cplx() if out is None else out
+        self._check_cplx(out)
+        check(lib().fft3d_r2c(self.h, _ptr(real), _ptr(out), _stream(stream)))
+        return out
+
+    def c2r(self, cplx, out=None, stream=None):
+        self._check_cplx(cplx)
+        out = self.empty_real() if out is None else out
+        self._check_real(out)
+        check(lib().fft3d_c2r(self.h, _ptr(cplx), _ptr(out), _stream(stream)))
+        return out
+
+    def parseval(self, real, cplx, stream=None):
+        out = (ctypes.c_double * 2)()
+        check(lib().fft3d_parseval(self.h, _ptr(real), _ptr(cplx), out, _stream(stream)))
+        return out[0], out[1]
+
+    def pass_times(self):
+        t = (ctypes.c_float * 6)()
+        check(lib().fft3d_pass_times(self.h, t))
+        return list(t)
+
+    def describe(self, p):
+        buf = ctypes.create_string_buffer(256)
+        check(lib().fft3d_describe(self.h, p, buf, 256))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().fft3d_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

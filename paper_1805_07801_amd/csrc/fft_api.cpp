@@ -1,0 +1,240 @@
+// 3D FFT plans: pass selection and the r2c / c2r pass sequences.
+//
+// Forward (paper, Section "Parallelization Strategy", steps 1-5 on one device):
+//   Z r2c  real_in -> cplx_out ;  Y c2c in place ;  X c2c in place with 1/(nx ny nz).
+// The two all-to-all exchanges of the pencil algorithm have no counterpart: the layout
+// is never permuted (Appendix A), the Y and X passes read strided columns.
+// Inverse: X c2c^-1 cplx_in -> workspace ; Y c2c^-1 in place ; Z c2r workspace -> real_out.
+#include <cstring>
+#include <new>
+
+#include "fft_api.hpp"
+#include "reduce.hpp"
+#include "tune.hpp"
+
+namespace tk {
+
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W) {
+    const StridedKernel *best = nullptr;
+    for (const auto &k : strided_kernels()) {
+        if (k.L != L || k.dt != dt) continue;
+        if (want_W > 0) {
+            if (k.W == want_W) return &k;
+            continue;
+        }
+        // default: 256 threads if available, else the candidate closest to it
+        if (!best || std::abs(k.nt - 256) < std::abs(best->nt - 256)) best = &k;
+    }
+    return best;
+}
+
+const ZKernel *pick_z(int N, tk_dtype dt) {
+    for (const auto &k : z_kernels())
+        if (k.N == N && k.dt == dt) return &k;
+    return nullptr;
+}
+
+tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
+                       long SI, const void *tw, int inv, double scale, hipStream_t s) {
+    StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale};
+    k->fn(a, s);
+    return launch_check("strided pass");
+}
+
+tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s) {
+    const long nzh = ax.nz / 2 + 1;
+    return strided_pass(ax.ky, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, inv, 1.0, s);
+}
+
+tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, double scale,
+                     hipStream_t s) {
+    const long nzh = ax.nz / 2 + 1;
+    const long cb = (long)ax.ny * nzh;
+    return strided_pass(ax.kx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, inv, scale, s);
+}
+
+tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s) {
+    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, scale};
+    ax.kz->r2c(a, s);
+    return launch_check("z r2c pass");
+}
+
+tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s) {
+    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, 1.0};
+    ax.kz->c2r(a, s);
+    return launch_check("z c2r pass");
+}
+
+tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_tune) {
+    if (!supported_len(nx) || !supported_len(ny) || !supported_len(nz))
+        return fail(TK_EUNSUPPORTED, "unsupported size %dx%dx%d (need 2^a or 3*2^a in [8,1024])", nx, ny, nz);
+    if (dt != TK_F32 && dt != TK_F64) return fail(TK_EUNSUPPORTED, "unsupported dtype %d", (int)dt);
+    ax->nx = nx;
+    ax->ny = ny;
+    ax->nz = nz;
+    ax->dt = dt;
+    tk_status st;
+    ax->twx = twiddle_table(nx, dt, &st);
+    if (!ax->twx) return st;
+    ax->twy = twiddle_table(ny, dt, &st);
+    if (!ax->twy) return st;
+    ax->twz = twiddle_table(nz, dt, &st);
+    if (!ax->twz) return st;
+    int wy = use_tune ? tuned_width(ny, dt, 1) : 0;
+    int wx = use_tune ? tuned_width(nx, dt, 2) : 0;
+    ax->ky = pick_strided(ny, dt, wy);
+    if (!ax->ky) ax->ky = pick_strided(ny, dt, 0);
+    ax->kx = pick_strided(nx, dt, wx);
+    if (!ax->kx) ax->kx = pick_strided(nx, dt, 0);
+    ax->kz = pick_z(nz, dt);
+    if (!ax->kx || !ax->ky || !ax->kz) return fail(TK_EUNSUPPORTED, "no kernel for %dx%dx%d", nx, ny, nz);
+    return TK_OK;
+}
+
+}  // namespace tk
+
+using namespace tk;
+
+struct tk_fft3d_s {
+    FftAxes ax;
+    int batch;
+    unsigned flags;
+    void *ws;
+    bool ws_owned;
+    hipEvent_t ev[8];
+    bool timing;
+};
+
+static size_t cplx_bytes(const tk_fft3d_s *p) {
+    size_t esz = p->ax.dt == TK_F32 ? 8 : 16;
+    return esz * (size_t)p->batch * p->ax.nx * p->ax.ny * (p->ax.nz / 2 + 1);
+}
+
+extern "C" tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
+                                       unsigned flags) {
+    if (!plan) return fail(TK_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (batch < 1) return fail(TK_EINVAL, "batch must be >= 1 (got %d)", batch);
+    tk_fft3d_s *p = new (std::nothrow) tk_fft3d_s();
+    if (!p) return fail(TK_ENOMEM, "host allocation failed");
+    tk_status st = axes_init(&p->ax, nx, ny, nz, dt, !(flags & TK_FFT_NO_TUNE));
+    if (st != TK_OK) {
+        delete p;
+        return st;
+    }
+    p->batch = batch;
+    p->flags = flags;
+    p->ws = nullptr;
+    p->ws_owned = false;
+    p->timing = (flags & TK_FFT_TIMING) != 0;
+    if (p->timing) {
+        for (int i = 0; i < 8; ++i) {
+            if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) hipEventDestroy(p->ev[j]);
+                delete p;
+                return fail(TK_EHIP, "hipEventCreate failed");
+            }
+        }
+    }
+    *plan = p;
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_workspace_size(tk_fft3d_t p, size_t *bytes) {
+    if (!p || !bytes) return fail(TK_EINVAL, "NULL argument");
+    *bytes = cplx_bytes(p);
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_set_workspace(tk_fft3d_t p, void *dev_ptr) {
+    if (!p) return fail(TK_EINVAL, "plan is NULL");
+    if (p->ws_owned && p->ws) hipFree(p->ws);
+    p->ws = dev_ptr;
+    p->ws_owned = false;
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out, void *stream) {
+    if (!p || !real_in || !cplx_out) return fail(TK_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const FftAxes &ax = p->ax;
+    const double scale = 1.0 / ((double)ax.nx * ax.ny * ax.nz);
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[0], s));
+    TK_TRY(fft_z_r2c(ax, real_in, cplx_out, p->batch, 1.0, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[1], s));
+    TK_TRY(fft_y_pass(ax, cplx_out, cplx_out, p->batch, 0, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[2], s));
+    TK_TRY(fft_x_pass(ax, cplx_out, cplx_out, p->batch, 0, scale, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[3], s));
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out, void *stream) {
+    if (!p || !cplx_in || !real_out) return fail(TK_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->ws) {
+        if (hipMalloc(&p->ws, cplx_bytes(p)) != hipSuccess) {
+            p->ws = nullptr;
+            return fail(TK_ENOMEM, "workspace allocation of %zu bytes failed", cplx_bytes(p));
+        }
+        p->ws_owned = true;
+    }
+    const FftAxes &ax = p->ax;
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[4], s));
+    TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[5], s));
+    TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[6], s));
+    TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s));
+    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[7], s));
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_pass_times(tk_fft3d_t p, float t[6]) {
+    if (!p || !t) return fail(TK_EINVAL, "NULL argument");
+    if (!p->timing) return fail(TK_ESTATE, "plan was created without TK_FFT_TIMING");
+    TK_HIP_CHECK(hipEventSynchronize(p->ev[3]));
+    TK_HIP_CHECK(hipEventSynchronize(p->ev[7]));
+    for (int i = 0; i < 3; ++i) {
+        TK_HIP_CHECK(hipEventElapsedTime(&t[i], p->ev[i], p->ev[i + 1]));
+        TK_HIP_CHECK(hipEventElapsedTime(&t[3 + i], p->ev[4 + i], p->ev[5 + i]));
+    }
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_parseval(tk_fft3d_t p, const void *real, const void *cplx, double out[2], void *stream) {
+    if (!p || !real || !cplx || !out) return fail(TK_EINVAL, "NULL argument");
+    const FftAxes &ax = p->ax;
+    long npts = (long)ax.nx * ax.ny * ax.nz;
+    double a = 0, b = 0;
+    TK_TRY(reduce_sumsq_real(real, npts, ax.dt, &a, (hipStream_t)stream));
+    TK_TRY(reduce_sumsq_half(cplx, (long)ax.nx * ax.ny, ax.nz, ax.dt, &b, (hipStream_t)stream));
+    out[0] = a / (double)npts;
+    out[1] = b;
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_describe(tk_fft3d_t p, int pass, char *buf, int len) {
+    if (!p || !buf || len <= 0) return fail(TK_EINVAL, "bad argument");
+    const FftAxes &ax = p->ax;
+    int n = 0;
+    if (pass == 0)
+        n = snprintf(buf, len, "z N=%d LPW=%d E=%d nt=%d lds=%d", ax.nz, ax.kz->LPW, ax.kz->E, ax.kz->nt, ax.kz->lds);
+    else if (pass == 1 || pass == 2) {
+        const StridedKernel *k = pass == 1 ? ax.ky : ax.kx;
+        n = snprintf(buf, len, "%c L=%d W=%d E=%d nt=%d lds=%d", pass == 1 ? 'y' : 'x', k->L, k->W, k->E, k->nt,
+                     k->lds);
+    } else
+        return fail(TK_EINVAL, "pass must be 0, 1 or 2");
+    (void)n;
+    return TK_OK;
+}
+
+extern "C" tk_status fft3d_plan_destroy(tk_fft3d_t p) {
+    if (!p) return TK_OK;
+    if (p->ws_owned && p->ws) hipFree(p->ws);
+    if (p->timing)
+        for (int i = 0; i < 8; ++i) hipEventDestroy(p->ev[i]);
+    delete p;
+    return TK_OK;
+}

@@ -1,0 +1,30 @@
+// Internal interface of the 3D transform passes, shared by the FFT plans and the solver.
+#pragma once
+
+#include "fft_kernels.hpp"
+
+namespace tk {
+
+// Kernels and twiddle tables for one (nx, ny, nz, dtype) grid.
+struct FftAxes {
+    int nx, ny, nz;
+    tk_dtype dt;
+    const void *twx, *twy, *twz;
+    const StridedKernel *kx, *ky;
+    const ZKernel *kz;
+};
+
+tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_tune);
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W);
+const ZKernel *pick_z(int N, tk_dtype dt);
+tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
+                       long SI, const void *tw, int inv, double scale, hipStream_t s);
+
+// Passes over `nfields` consecutive spectral fields [nfields][nx][ny][nz/2+1].
+tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s);
+tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, double scale,
+                     hipStream_t s);
+tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s);
+tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s);
+
+}  // namespace tk

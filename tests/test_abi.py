@@ -1,0 +1,56 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol tk.h declares,
+and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1805_07801_amd as tk
+    if not os.path.exists(tk.LIB_PATH):
+        from paper_1805_07801_amd import build
+        build.build(force=False)
+    return tk.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "fft3d_r2c" in names and "ns_step" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_text(lib):
+    assert lib.tk_version() >= 10000
+    assert isinstance(lib.tk_last_error(), bytes)
+
+
+@pytest.mark.parametrize("n", [0, 7, 10, 2048, 9, 6, 1536])
+def test_plan_rejects_unsupported_sizes(lib, n):
+    import paper_1805_07801_amd as tk
+    h = ctypes.c_void_p()
+    st = lib.fft3d_plan_create(ctypes.byref(h), n, 16, 16, 1, tk.TK_F32, 0)
+    assert st == tk.TK_EUNSUPPORTED
+    assert h.value is None
+    assert b"unsupported" in lib.tk_last_error()
+
+
+def test_plan_rejects_bad_arguments(lib):
+    import paper_1805_07801_amd as tk
+    h = ctypes.c_void_p()
+    assert lib.fft3d_plan_create(None, 16, 16, 16, 1, tk.TK_F32, 0) == tk.TK_EINVAL
+    assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 0, tk.TK_F32, 0) == tk.TK_EINVAL
+    assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 1, 7, 0) == tk.TK_EUNSUPPORTED
+    assert lib.fft3d_r2c(None, None, None, None) == tk.TK_EINVAL
+    assert lib.fft3d_plan_destroy(None) == tk.TK_OK

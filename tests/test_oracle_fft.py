@@ -140,3 +140,16 @@ def test_hermitian_planes_and_parseval():
         assert np.max(np.abs(P - Pc)) <= 1e-15
     a, b = diag.parseval(f, F)
     assert abs(a - b) <= 1e-13 * a
+
+
+def test_sampled_definitions_match_full_transform():
+    """dft_at / idft_at evaluate the definitions directly; they agree with the full transform."""
+    n = 24
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((n, 12, 16))
+    F = fft.rfft3(f)
+    ks = [(0, 0, 0), (3, 5, 2), (23, 11, 8), (12, 6, 7)]
+    got = fft.dft_at(f, ks)
+    assert np.max(np.abs(got - np.array([F[k] for k in ks]))) <= 1e-15
+    xs = [(0, 0, 0), (5, 7, 3), (23, 11, 15)]
+    assert np.max(np.abs(fft.idft_at(F, 16, xs) - np.array([f[x] for x in xs]))) <= 1e-13
