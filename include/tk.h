@@ -95,8 +95,10 @@ tk_status fft3d_c2r(tk_fft3d_t plan, const void *cplx_in, void *real_out, void *
 tk_status fft3d_parseval(tk_fft3d_t plan, const void *real, const void *cplx, double out[2],
                          void *stream);
 
-/* Per-pass durations in ms of the last r2c (t[0..2] = Z, Y, X) and c2r (t[3..5] = X, Y,
- * Z), for a plan created with TK_FFT_TIMING.  Synchronises. */
+/* Average per-pass durations in ms (t[0..2] = Z, Y, X of r2c; t[3..5] = X, Y, Z of c2r)
+ * over the calls made since the previous query (at most the last 256), for a plan created
+ * with TK_FFT_TIMING, which records HIP events around every pass on the call's stream
+ * without synchronising.  This call synchronises those events and resets the average. */
 tk_status fft3d_pass_times(tk_fft3d_t plan, float t[6]);
 
 /* Describe the tile configuration the plan uses for pass p (0 = Z, 1 = Y, 2 = X) as
@@ -104,6 +106,29 @@ tk_status fft3d_pass_times(tk_fft3d_t plan, float t[6]);
 tk_status fft3d_describe(tk_fft3d_t plan, int pass, char *buf, int len);
 
 tk_status fft3d_plan_destroy(tk_fft3d_t plan);
+
+/* ---- autotuner (tile shapes of the three passes) ----------------------------------------
+ * Runs every compiled tile candidate of each pass of an (nx, ny, nz, batch, dt) grid on
+ * a pseudo-random field on the current device, timed with HIP events (median of iters
+ * launches).  A candidate is admitted only if its output matches the default tile's
+ * to relative L2 1e-5 (FP32) / 1e-12 (FP64).  The fastest admitted tile per (length,
+ * dtype, pass) goes into a process-wide table that plans created afterwards use (unless
+ * created with TK_FFT_NO_TUNE).  Allocates and frees three spectral-field buffers.
+ * report (may be NULL) receives one text line per candidate.  Synchronises. */
+tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int iters, char *report,
+                         int report_len);
+
+/* Force the tile of (L, dt, pass): pass 0 = Z (a = threads per workgroup), 1 = Y and
+ * 2 = X (a = columns per tile); E = points per thread.  a <= 0 removes the entry.
+ * TK_EUNSUPPORTED if no such tile is compiled. */
+tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E);
+
+/* Forget every tuned tile. */
+tk_status fft3d_tune_clear(void);
+
+/* Number of compiled tile candidates of (L, dt, pass); the first `cap` are written to
+ * a[] and E[] (either may be NULL). */
+int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int cap);
 
 /* ------------------------------------------------------------------------------------
  * Pseudo-spectral incompressible Navier-Stokes in the periodic (2 pi)^3 box.

@@ -37,6 +37,10 @@ def _declare(L):
         "fft3d_pass_times": ([vp, P(ctypes.c_float)], i),
         "fft3d_describe": ([vp, i, ctypes.c_char_p, i], i),
         "fft3d_plan_destroy": ([vp], i),
+        "fft3d_autotune": ([i, i, i, i, i, i, ctypes.c_char_p, i], i),
+        "fft3d_tune_set": ([i, i, i, i, i], i),
+        "fft3d_tune_clear": ([], i),
+        "fft3d_tile_candidates": ([i, i, i, P(i), P(i), i], i),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -83,6 +87,57 @@ def _dtype_code(dtype):
     if dtype in (torch.float64, torch.complex128):
         return TK_F64
     raise TkError(TK_EUNSUPPORTED, "dtype %s" % dtype)
+
+
+def autotune(nx, ny=None, nz=None, batch=1, dtype=None, iters=5):
+    """Time every tile candidate of each pass on this GPU and keep the fastest one that
+    matches the default tile (see fft3d_autotune).  Returns the text report."""
+    import torch
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(lib().fft3d_autotune(nx, ny, nz, batch, _dtype_code(dtype or torch.float32), iters, buf, 1 << 16))
+    return buf.value.decode()
+
+
+def tile_candidates(L, dtype, pass_):
+    """[(a, E)] compiled tile candidates of (L, dtype, pass): pass 0 = Z (a = threads),
+    1 = Y and 2 = X (a = columns per tile)."""
+    code = _dtype_code(dtype)
+    n = lib().fft3d_tile_candidates(L, code, pass_, None, None, 0)
+    a = (ctypes.c_int * max(n, 1))()
+    e = (ctypes.c_int * max(n, 1))()
+    lib().fft3d_tile_candidates(L, code, pass_, a, e, n)
+    return [(a[i], e[i]) for i in range(n)]
+
+
+def tune_set(L, dtype, pass_, a, E):
+    check(lib().fft3d_tune_set(L, _dtype_code(dtype), pass_, a, E))
+
+
+def tune_clear():
+    check(lib().fft3d_tune_clear())
+
+
+def tune_save(path, entries):
+    """Persist tuned tiles [(L, dtype_code, pass, a, E)] as JSON lines."""
+    import json
+    with open(path, "w") as f:
+        for L, dt, p, a, E in entries:
+            f.write(json.dumps({"L": L, "dtype": dt, "pass": p, "a": a, "E": E}) + "\n")
+
+
+def tune_load(path):
+    """Apply tuned tiles saved by tune_save; returns how many were applied."""
+    import json
+    n = 0
+    with open(path) as f:
+        for line in f:
+            if line.strip():
+                e = json.loads(line)
+                check(lib().fft3d_tune_set(e["L"], e["dtype"], e["pass"], e["a"], e["E"]))
+                n += 1
+    return n
 
 
 class FFT3D:

@@ -88,16 +88,24 @@ const void *twiddle_table(int n, tk_dtype dt, tk_status *st) {
     return p;
 }
 
-void register_f32(std::vector<StridedKernel> &s, std::vector<ZKernel> &z);
-void register_f64(std::vector<StridedKernel> &s, std::vector<ZKernel> &z);
+#define TK_REG(name) void name(std::vector<StridedKernel> &s, std::vector<ZKernel> &z);
+TK_REG(register_f32_a) TK_REG(register_f32_b) TK_REG(register_f32_c) TK_REG(register_f32_d)
+TK_REG(register_f32_e) TK_REG(register_f32_f) TK_REG(register_f64_a) TK_REG(register_f64_b)
+#undef TK_REG
 
 static void build_registry(std::vector<StridedKernel> *&s, std::vector<ZKernel> *&z) {
     static std::vector<StridedKernel> S;
     static std::vector<ZKernel> Z;
     static std::once_flag once;
     std::call_once(once, [] {
-        register_f32(S, Z);
-        register_f64(S, Z);
+        register_f32_a(S, Z);
+        register_f32_b(S, Z);
+        register_f32_c(S, Z);
+        register_f32_d(S, Z);
+        register_f32_e(S, Z);
+        register_f32_f(S, Z);
+        register_f64_a(S, Z);
+        register_f64_b(S, Z);
     });
     s = &S;
     z = &Z;

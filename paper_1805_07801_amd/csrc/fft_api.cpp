@@ -14,24 +14,33 @@
 
 namespace tk {
 
-const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W) {
+// Default tile: the widest W (longest contiguous runs) whose LDS tile still lets two
+// workgroups share a CU; ties go to fewer threads.
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E) {
     const StridedKernel *best = nullptr;
     for (const auto &k : strided_kernels()) {
         if (k.L != L || k.dt != dt) continue;
         if (want_W > 0) {
-            if (k.W == want_W) return &k;
+            if (k.W == want_W && k.E == want_E) return &k;
             continue;
         }
-        // default: 256 threads if available, else the candidate closest to it
-        if (!best || std::abs(k.nt - 256) < std::abs(best->nt - 256)) best = &k;
+        auto score = [](const StridedKernel &q) { return (q.lds <= 81920 ? 100000 : 0) + q.W * 10 - q.nt / 256; };
+        if (!best || score(k) > score(*best)) best = &k;
     }
     return best;
 }
 
-const ZKernel *pick_z(int N, tk_dtype dt) {
-    for (const auto &k : z_kernels())
-        if (k.N == N && k.dt == dt) return &k;
-    return nullptr;
+const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E) {
+    const ZKernel *best = nullptr;
+    for (const auto &k : z_kernels()) {
+        if (k.N != N || k.dt != dt) continue;
+        if (want_nt > 0) {
+            if (k.nt == want_nt && k.E == want_E) return &k;
+            continue;
+        }
+        if (!best || std::abs(k.nt - 256) + k.E < std::abs(best->nt - 256) + best->E) best = &k;
+    }
+    return best;
 }
 
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
@@ -80,13 +89,18 @@ tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_t
     if (!ax->twy) return st;
     ax->twz = twiddle_table(nz, dt, &st);
     if (!ax->twz) return st;
-    int wy = use_tune ? tuned_width(ny, dt, 1) : 0;
-    int wx = use_tune ? tuned_width(nx, dt, 2) : 0;
-    ax->ky = pick_strided(ny, dt, wy);
-    if (!ax->ky) ax->ky = pick_strided(ny, dt, 0);
-    ax->kx = pick_strided(nx, dt, wx);
-    if (!ax->kx) ax->kx = pick_strided(nx, dt, 0);
-    ax->kz = pick_z(nz, dt);
+    TileChoice ty{}, tx{}, tz{};
+    if (use_tune) {
+        ty = tuned_tile(ny, dt, 1);
+        tx = tuned_tile(nx, dt, 2);
+        tz = tuned_tile(nz, dt, 0);
+    }
+    ax->ky = pick_strided(ny, dt, ty.a, ty.E);
+    if (!ax->ky) ax->ky = pick_strided(ny, dt, 0, 0);
+    ax->kx = pick_strided(nx, dt, tx.a, tx.E);
+    if (!ax->kx) ax->kx = pick_strided(nx, dt, 0, 0);
+    ax->kz = pick_z(nz, dt, tz.a, tz.E);
+    if (!ax->kz) ax->kz = pick_z(nz, dt, 0, 0);
     if (!ax->kx || !ax->ky || !ax->kz) return fail(TK_EUNSUPPORTED, "no kernel for %dx%dx%d", nx, ny, nz);
     return TK_OK;
 }
@@ -95,14 +109,20 @@ tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_t
 
 using namespace tk;
 
+// With TK_FFT_TIMING a plan records HIP events around every pass into a ring of
+// NSET sets (no synchronisation); fft3d_pass_times averages the sets recorded since
+// its previous call.
+static const int NSET = 256;
+
 struct tk_fft3d_s {
     FftAxes ax;
     int batch;
     unsigned flags;
     void *ws;
     bool ws_owned;
-    hipEvent_t ev[8];
     bool timing;
+    std::vector<hipEvent_t> ev;  // NSET x 8
+    int nr2c, nc2r;
 };
 
 static size_t cplx_bytes(const tk_fft3d_s *p) {
@@ -127,8 +147,10 @@ extern "C" tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz,
     p->ws = nullptr;
     p->ws_owned = false;
     p->timing = (flags & TK_FFT_TIMING) != 0;
+    p->nr2c = p->nc2r = 0;
     if (p->timing) {
-        for (int i = 0; i < 8; ++i) {
+        p->ev.resize(NSET * 8);
+        for (int i = 0; i < NSET * 8; ++i) {
             if (hipEventCreate(&p->ev[i]) != hipSuccess) {
                 for (int j = 0; j < i; ++j) hipEventDestroy(p->ev[j]);
                 delete p;
@@ -159,13 +181,17 @@ extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out
     hipStream_t s = (hipStream_t)stream;
     const FftAxes &ax = p->ax;
     const double scale = 1.0 / ((double)ax.nx * ax.ny * ax.nz);
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[0], s));
+    hipEvent_t *ev = p->timing ? &p->ev[(p->nr2c % NSET) * 8] : nullptr;
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[0], s));
     TK_TRY(fft_z_r2c(ax, real_in, cplx_out, p->batch, 1.0, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[1], s));
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[1], s));
     TK_TRY(fft_y_pass(ax, cplx_out, cplx_out, p->batch, 0, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[2], s));
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[2], s));
     TK_TRY(fft_x_pass(ax, cplx_out, cplx_out, p->batch, 0, scale, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[3], s));
+    if (ev) {
+        TK_HIP_CHECK(hipEventRecord(ev[3], s));
+        p->nr2c++;
+    }
     return TK_OK;
 }
 
@@ -180,25 +206,48 @@ extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out
         p->ws_owned = true;
     }
     const FftAxes &ax = p->ax;
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[4], s));
+    hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
     TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[5], s));
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
     TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[6], s));
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
     TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s));
-    if (p->timing) TK_HIP_CHECK(hipEventRecord(p->ev[7], s));
+    if (ev) {
+        TK_HIP_CHECK(hipEventRecord(ev[7], s));
+        p->nc2r++;
+    }
     return TK_OK;
 }
 
 extern "C" tk_status fft3d_pass_times(tk_fft3d_t p, float t[6]) {
     if (!p || !t) return fail(TK_EINVAL, "NULL argument");
     if (!p->timing) return fail(TK_ESTATE, "plan was created without TK_FFT_TIMING");
-    TK_HIP_CHECK(hipEventSynchronize(p->ev[3]));
-    TK_HIP_CHECK(hipEventSynchronize(p->ev[7]));
-    for (int i = 0; i < 3; ++i) {
-        TK_HIP_CHECK(hipEventElapsedTime(&t[i], p->ev[i], p->ev[i + 1]));
-        TK_HIP_CHECK(hipEventElapsedTime(&t[3 + i], p->ev[4 + i], p->ev[5 + i]));
+    const int nf = std::min(p->nr2c, NSET), ni = std::min(p->nc2r, NSET);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < nf; ++k) {
+        hipEvent_t *ev = &p->ev[k * 8];
+        TK_HIP_CHECK(hipEventSynchronize(ev[3]));
+        for (int i = 0; i < 3; ++i) {
+            float ms;
+            TK_HIP_CHECK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            acc[i] += ms;
+        }
     }
+    for (int k = 0; k < ni; ++k) {
+        hipEvent_t *ev = &p->ev[k * 8];
+        TK_HIP_CHECK(hipEventSynchronize(ev[7]));
+        for (int i = 0; i < 3; ++i) {
+            float ms;
+            TK_HIP_CHECK(hipEventElapsedTime(&ms, ev[4 + i], ev[5 + i]));
+            acc[3 + i] += ms;
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        t[i] = nf ? (float)(acc[i] / nf) : 0.f;
+        t[3 + i] = ni ? (float)(acc[3 + i] / ni) : 0.f;
+    }
+    p->nr2c = p->nc2r = 0;
     return TK_OK;
 }
 
@@ -233,8 +282,7 @@ extern "C" tk_status fft3d_describe(tk_fft3d_t p, int pass, char *buf, int len) 
 extern "C" tk_status fft3d_plan_destroy(tk_fft3d_t p) {
     if (!p) return TK_OK;
     if (p->ws_owned && p->ws) hipFree(p->ws);
-    if (p->timing)
-        for (int i = 0; i < 8; ++i) hipEventDestroy(p->ev[i]);
+    for (hipEvent_t e : p->ev) hipEventDestroy(e);
     delete p;
     return TK_OK;
 }

@@ -15,8 +15,9 @@ struct FftAxes {
 };
 
 tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_tune);
-const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W);
-const ZKernel *pick_z(int N, tk_dtype dt);
+// want_W / want_nt = 0 selects the default candidate.
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E);
+const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E);
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
                        long SI, const void *tw, int inv, double scale, hipStream_t s);
 

@@ -1,12 +1,15 @@
 // Device building blocks of the 1D transforms: radix-2/3/4/8 butterflies and Stockham
-// autosort stages over a line that lives in LDS.
+// autosort stages with the line held in registers between LDS exchanges.
 //
-// A line of L complex points is transformed by TPL = L / E threads; each thread owns E
-// points per stage (E / R butterflies of radix R).  Stage s has radix R and span NS (the
-// product of the radices before it): butterfly j takes x[j + m L/R], m < R, multiplies
-// leg m by W_{NS R}^{(j mod NS) m}, applies the R-point DFT and writes leg m to
-// (j - j mod NS) R + j mod NS + m NS.  After the last stage the line is in natural
-// order (Stockham autosort), so no bit reversal pass exists.
+// A line of L complex points is transformed by TPL = L / E threads; thread jt owns the
+// E points x[jt + i TPL], i < E.  Stage s has radix R and span NS (product of the
+// radices before it): butterfly j takes x[j + m L/R], m < R, multiplies leg m by
+// W_{NS R}^{(j mod NS) m}, applies the R-point DFT and sends leg m to position
+// (j - j mod NS) R + j mod NS + m NS.  With the thread's butterflies j = jt + b TPL,
+// b < E/R, every stage reads exactly the thread's own points x[jt + i TPL], and the
+// last stage (NS = L/R) writes exactly them: so loads from and stores to global memory
+// go straight to registers and only the exchanges between stages pass through LDS.
+// After the last stage the line is in natural order (Stockham autosort).
 #pragma once
 
 #include "common.hpp"
@@ -66,112 +69,132 @@ constexpr bool rplan_ok(int L, int E) {
 template <int R, typename C> struct Dft;
 
 template <typename C> struct Dft<2, C> {
-    static __device__ __forceinline__ void run(C *v) {
-        C a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
+    static __device__ __forceinline__ void run(C &a, C &b) {
+        C t = a;
+        a = cadd(t, b);
+        b = csub(t, b);
     }
 };
 
 template <typename C> struct Dft<3, C> {
-    static __device__ __forceinline__ void run(C *v) {
-        using T = decltype(v[0].x);
+    static __device__ __forceinline__ void run(C &x0, C &x1, C &x2) {
+        using T = decltype(x0.x);
         const T s3 = (T)0.86602540378443864676372317075294;  // sin(2 pi / 3)
-        C a = v[0];
-        C p = cadd(v[1], v[2]);
-        C m = csub(v[1], v[2]);
-        C t = a;
+        C p = cadd(x1, x2);
+        C m = csub(x1, x2);
+        C t = x0;
         t.x -= (T)0.5 * p.x;
         t.y -= (T)0.5 * p.y;
-        v[0] = cadd(a, p);
-        // y1 = t - i s3 m ; y2 = t + i s3 m
-        C q;
+        x0 = cadd(x0, p);
+        C q;  // -i s3 m
         q.x = s3 * m.y;
-        q.y = -s3 * m.x;  // -i s3 m
-        v[1] = cadd(t, q);
-        v[2] = csub(t, q);
+        q.y = -s3 * m.x;
+        x1 = cadd(t, q);
+        x2 = csub(t, q);
     }
 };
 
 template <typename C> struct Dft<4, C> {
-    static __device__ __forceinline__ void run(C *v) {
-        C t0 = cadd(v[0], v[2]);
-        C t1 = csub(v[0], v[2]);
-        C t2 = cadd(v[1], v[3]);
-        C t3 = cmul_mi(csub(v[1], v[3]));
-        v[0] = cadd(t0, t2);
-        v[2] = csub(t0, t2);
-        v[1] = cadd(t1, t3);
-        v[3] = csub(t1, t3);
+    static __device__ __forceinline__ void run(C &x0, C &x1, C &x2, C &x3) {
+        C t0 = cadd(x0, x2);
+        C t1 = csub(x0, x2);
+        C t2 = cadd(x1, x3);
+        C t3 = cmul_mi(csub(x1, x3));
+        x0 = cadd(t0, t2);
+        x2 = csub(t0, t2);
+        x1 = cadd(t1, t3);
+        x3 = csub(t1, t3);
     }
 };
 
 template <typename C> struct Dft<8, C> {
-    static __device__ __forceinline__ void run(C *v) {
-        using T = decltype(v[0].x);
+    static __device__ __forceinline__ void run(C &x0, C &x1, C &x2, C &x3, C &x4, C &x5, C &x6, C &x7) {
+        using T = decltype(x0.x);
         const T r2 = (T)0.70710678118654752440084436210485;
-        C e[4] = {v[0], v[2], v[4], v[6]};
-        C o[4] = {v[1], v[3], v[5], v[7]};
-        Dft<4, C>::run(e);
-        Dft<4, C>::run(o);
-        // o[k] *= W8^k, W8 = (1 - i)/sqrt2
+        Dft<4, C>::run(x0, x2, x4, x6);  // even legs -> E0..E3 in x0, x2, x4, x6
+        Dft<4, C>::run(x1, x3, x5, x7);  // odd legs  -> O0..O3 in x1, x3, x5, x7
         C o1, o3;
-        o1.x = r2 * (o[1].x + o[1].y);
-        o1.y = r2 * (o[1].y - o[1].x);
-        C o2 = cmul_mi(o[2]);
-        o3.x = r2 * (o[3].y - o[3].x);
-        o3.y = -r2 * (o[3].x + o[3].y);
-        v[0] = cadd(e[0], o[0]);
-        v[4] = csub(e[0], o[0]);
-        v[1] = cadd(e[1], o1);
-        v[5] = csub(e[1], o1);
-        v[2] = cadd(e[2], o2);
-        v[6] = csub(e[2], o2);
-        v[3] = cadd(e[3], o3);
-        v[7] = csub(e[3], o3);
+        o1.x = r2 * (x3.x + x3.y);  // O1 W8
+        o1.y = r2 * (x3.y - x3.x);
+        C o2 = cmul_mi(x5);         // O2 W8^2
+        o3.x = r2 * (x7.y - x7.x);  // O3 W8^3
+        o3.y = -r2 * (x7.x + x7.y);
+        C e0 = x0, e1 = x2, e2 = x4, e3 = x6, o0 = x1;
+        x0 = cadd(e0, o0);
+        x4 = csub(e0, o0);
+        x1 = cadd(e1, o1);
+        x5 = csub(e1, o1);
+        x2 = cadd(e2, o2);
+        x6 = csub(e2, o2);
+        x3 = cadd(e3, o3);
+        x7 = csub(e3, o3);
     }
 };
 
-// ---- one Stockham stage on an LDS line -----------------------------------------------------------
-// d: the line's element 0; element e at d[e * ES].  tw: table of W_TB^j with TB = L * TS.
-template <typename T, int L, int R, int NS, int TPL, int ES, int TS>
-__device__ __forceinline__ void stockham_stage(V2<T> *d, int jt, const V2<T> *__restrict__ tw) {
+// Butterfly b of a stage: legs v[b + m NB], m < R.
+template <int R, int NB, typename C> __device__ __forceinline__ void dft_legs(C *v, int b) {
+    if constexpr (R == 2) Dft<2, C>::run(v[b], v[b + NB]);
+    else if constexpr (R == 3) Dft<3, C>::run(v[b], v[b + NB], v[b + 2 * NB]);
+    else if constexpr (R == 4) Dft<4, C>::run(v[b], v[b + NB], v[b + 2 * NB], v[b + 3 * NB]);
+    else Dft<8, C>::run(v[b], v[b + NB], v[b + 2 * NB], v[b + 3 * NB], v[b + 4 * NB], v[b + 5 * NB],
+                        v[b + 6 * NB], v[b + 7 * NB]);
+}
+
+// ---- LDS addressing ---------------------------------------------------------------------------
+// Contiguous lines (ES == 1): one padding slot every 32 complex values, so that the
+// stride-R scatter of a stage spreads over the banks.
+template <int ES> __device__ __forceinline__ int lds_at(int e) {
+    if constexpr (ES == 1) return e + (e >> 5);
+    else return e * ES;
+}
+template <int L> constexpr int lds_line_len() { return L + (L >> 5) + 1; }
+
+// ---- the transform -------------------------------------------------------------------------------
+// v[i] = x[jt + i TPL] on entry, X[jt + i TPL] on exit (forward DFT, unscaled).
+// d: this line's LDS (element e at d[lds_at<ES>(e)]), tw: LDS table with W_L^j at
+// tw[j * TS].
+// Every thread of the workgroup must call it (it contains barriers).  On exit the LDS
+// line may be reused only after a barrier.
+template <typename T, int L, int E, int ES, int TS = 1, int S = 0>
+__device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw) {
     using C = V2<T>;
-    constexpr int NB = L / (R * TPL);
-    static_assert(NB * R * TPL == L, "stage does not tile the line");
-    C v[NB][R];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = jt + b * TPL;
-#pragma unroll
-        for (int m = 0; m < R; ++m) v[b][m] = d[(j + m * (L / R)) * ES];
-    }
-    __syncthreads();
+    constexpr RPlan P = make_rplan(L, E);
+    constexpr int R = P.r[S];
+    constexpr int NS = rplan_span(P, S);
+    constexpr int NB = E / R;
+    constexpr int TPL = L / E;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = jt + b * TPL;
         const int k = j % NS;
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int m = 1; m < R; ++m) v[b][m] = cmul(v[b][m], tw[k * m * (L / (NS * R)) * TS]);
+            for (int m = 1; m < R; ++m) v[b + m * NB] = cmul(v[b + m * NB], tw[k * m * (L / (NS * R)) * TS]);
         }
-        Dft<R, C>::run(v[b]);
-        const int base = (j - k) * R + k;
-#pragma unroll
-        for (int m = 0; m < R; ++m) d[(base + m * NS) * ES] = v[b][m];
+        dft_legs<R, NB>(v, b);
     }
-    __syncthreads();
+    if constexpr (S + 1 < P.n) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = jt + b * TPL;
+            const int k = j % NS;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
+        __syncthreads();
+        line_fft<T, L, E, ES, TS, S + 1>(v, d, jt, tw);
+    }
 }
 
-template <typename T, int L, int E, int ES, int TS, int S = 0>
-__device__ __forceinline__ void line_fft(V2<T> *d, int jt, const V2<T> *__restrict__ tw) {
-    constexpr RPlan P = make_rplan(L, E);
-    if constexpr (S < P.n) {
-        constexpr int R = P.r[S];
-        constexpr int NS = rplan_span(P, S);
-        stockham_stage<T, L, R, NS, L / E, ES, TS>(d, jt, tw);
-        line_fft<T, L, E, ES, TS, S + 1>(d, jt, tw);
-    }
+// Cooperative copy of a twiddle table of n entries into LDS; the caller places a
+// barrier before its first use.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(V2<T> *dst, const V2<T> *__restrict__ src, int n, int tid, int nt) {
+    for (int j = tid; j < n; j += nt) dst[j] = src[j];
 }
 
 }  // namespace tk

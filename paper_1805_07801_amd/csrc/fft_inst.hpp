@@ -1,4 +1,5 @@
-// Registry builders: instantiate every pass kernel for the supported line lengths.
+// Registry builders: instantiate the pass kernels for the supported line lengths and
+// every tile-shape candidate that fits.
 #pragma once
 
 #include "fft_kernels.hpp"
@@ -9,24 +10,39 @@ template <typename T> constexpr tk_dtype dtype_of();
 template <> constexpr tk_dtype dtype_of<float>() { return TK_F32; }
 template <> constexpr tk_dtype dtype_of<double>() { return TK_F64; }
 
-template <typename T, int L, int C> void add_strided(std::vector<StridedKernel> &v) {
-    constexpr int E = default_E(L);
-    constexpr int W = strided_Wb(L, E) << C;
-    static_assert(rplan_ok(L, E), "bad radix plan");
-    if constexpr (strided_ok<T>(L, E, W))
-        v.push_back({L, dtype_of<T>(), W, E, W * (L / E), (int)(L * W * sizeof(V2<T>)), &launch_strided<T, L, E, W>});
+template <typename T, int L, int CE, int CN> void add_strided(std::vector<StridedKernel> &v) {
+    if constexpr (strided_cand_ok<T>(L, CE, CN)) {
+        constexpr int E = default_E(L) << CE;
+        constexpr int NT = 256 << CN;
+        constexpr int W = NT * E / L;
+        v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided<T, L, E, W>});
+    }
 }
 
-template <typename T, int N> void add_z(std::vector<ZKernel> &v) {
-    constexpr int L = N / 2;
-    constexpr int E = default_E(L);
-    constexpr int LPW = z_LPW(L, E);
-    static_assert(rplan_ok(L, E), "bad radix plan");
-    v.push_back({N, dtype_of<T>(), LPW, E, LPW * (L / E), (int)(LPW * (L + 1) * sizeof(V2<T>)),
-                 &launch_z_r2c<T, L, E, LPW>, &launch_z_c2r<T, L, E, LPW>});
+template <typename T, int N, int CE, int CN> void add_z(std::vector<ZKernel> &v) {
+    if constexpr (z_cand_ok<T>(N, CE, CN)) {
+        constexpr int L = N / 2;
+        constexpr int E = default_E(L) << CE;
+        constexpr int NT = 256 << CN;
+        constexpr int LPW = NT / (L / E);
+        v.push_back({N, dtype_of<T>(), LPW, E, NT, (int)((LPW * lds_line_len<L>() + 2 * L) * sizeof(V2<T>)),
+                     &launch_z_r2c<T, L, E, LPW>, &launch_z_c2r<T, L, E, LPW>});
+    }
 }
 
-// The supported lengths: 2^a and 3 * 2^a in [8, 1024].
-#define TK_FOR_EACH_LEN(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+// FP32: E in {Ed, 2 Ed, 4 Ed} x NT in {256, 512, 1024} for strided passes,
+//       E in {Ed, 2 Ed} x NT in {256, 512} for Z passes.
+template <int L> void add_all_f32(std::vector<StridedKernel> &s, std::vector<ZKernel> &z) {
+    add_strided<float, L, 0, 0>(s); add_strided<float, L, 0, 1>(s); add_strided<float, L, 0, 2>(s);
+    add_strided<float, L, 1, 0>(s); add_strided<float, L, 1, 1>(s); add_strided<float, L, 1, 2>(s);
+    add_strided<float, L, 2, 0>(s); add_strided<float, L, 2, 1>(s);
+    add_z<float, L, 0, 0>(z); add_z<float, L, 0, 1>(z); add_z<float, L, 1, 0>(z); add_z<float, L, 1, 1>(z);
+}
+
+// FP64: E = Ed, NT in {256, 512} (strided) and NT = 256 (Z).
+template <int L> void add_all_f64(std::vector<StridedKernel> &s, std::vector<ZKernel> &z) {
+    add_strided<double, L, 0, 0>(s); add_strided<double, L, 0, 1>(s);
+    add_z<double, L, 0, 0>(z);
+}
 
 }  // namespace tk

@@ -4,9 +4,10 @@
 //         along the contiguous z axis -> N/2+1 complex, as an N/2-point complex FFT of
 //         the packed (even, odd) samples plus the real-FFT split; the inverse undoes it.
 // Y and X passes (steps 3 and 5): complex transforms along a strided axis.  The layout
-//         never changes (Appendix A's transpose-free scheme): a workgroup stages a tile
-//         of W neighbouring columns x L points in LDS, so every global access is a run
-//         of W consecutive complex values.
+//         never changes (Appendix A's transpose-free scheme): a workgroup owns a tile of
+//         W neighbouring columns x L points, so every global access is a run of W
+//         consecutive complex values; the columns' points stay in registers and only the
+//         exchanges between radix stages go through LDS.
 #pragma once
 
 #include "fft_core.hpp"
@@ -54,37 +55,43 @@ const std::vector<StridedKernel> &strided_kernels();
 const std::vector<ZKernel> &z_kernels();
 
 // ---- strided complex pass ----------------------------------------------------------------------
+template <int L, int E, int W> constexpr int strided_es() { return W + 1; }
+
 template <typename T, int L, int E, int W>
 __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
-                                                         long SO, long SI, const V2<T> *__restrict__ tw,
+                                                         long SO, long SI, const V2<T> *__restrict__ twg,
                                                          int inv, T scale) {
     using C = V2<T>;
     constexpr int TPL = L / E;
-    constexpr int ES = W;
+    constexpr int NT = W * TPL;
+    constexpr int ES = strided_es<L, E, W>();
     __shared__ C lds[L * ES];
+    __shared__ C tw[L];
     const int tid = threadIdx.x;
     const int col = tid % W;
     const int jt = tid / W;
     const long c = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
     const bool valid = c < ncols;
     const long base = valid ? (c / CB) * SO + (c % CB) : 0;
+    C v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int row = jt + i * TPL;
-        C v = valid ? src[base + row * SI] : mk<T>(0, 0);
-        if (inv) v.y = -v.y;
-        lds[row * ES + col] = v;
+        C x = valid ? src[base + (long)(jt + i * TPL) * SI] : mk<T>(0, 0);
+        if (inv) x.y = -x.y;
+        v[i] = x;
     }
+    load_twiddles<T>(tw, twg, L, tid, NT);
     __syncthreads();
-    line_fft<T, L, E, ES, 1>(lds + col, jt, tw);
+    line_fft<T, L, E, ES>(v, lds + col, jt, tw);
+    if (valid) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int row = jt + i * TPL;
-        C v = lds[row * ES + col];
-        if (inv) v.y = -v.y;
-        v.x *= scale;
-        v.y *= scale;
-        if (valid) dst[base + row * SI] = v;
+        for (int i = 0; i < E; ++i) {
+            C x = v[i];
+            if (inv) x.y = -x.y;
+            x.x *= scale;
+            x.y *= scale;
+            dst[base + (long)(jt + i * TPL) * SI] = x;
+        }
     }
 }
 
@@ -97,108 +104,95 @@ void launch_strided(const StridedArgs &a, hipStream_t s) {
 }
 
 // ---- Z pass: real lines <-> half spectra ----------------------------------------------------------
-// LDS line stride: L + 1 entries (room for the Nyquist value of the c2r input).
+// Thread (ln, jt) of a workgroup handles line l0 + ln, points jt + i TPL of the L = N/2
+// complex values z[n] = x[2n] + i x[2n+1].
+// r2c split:  X[k] = 1/2 (Z[k] + conj Z[L-k]) - i/2 W_N^k (Z[k] - conj Z[L-k]),  k < L;
+//             X[L] = Re Z[0] - Im Z[0].
+// c2r merge:  Z'[k] = (X[k] + conj X[L-k]) + i conj(W_N^k) (X[k] - conj X[L-k]), with
+//             only the real parts of X[0] and X[L] taken; z = sum_k Z'[k] exp(+2 pi i kn/L)
+//             done as conj(DFT(conj Z')); x[2n] = Re z[n], x[2n+1] = Im z[n].
 template <typename T, int L, int E, int LPW>
 __global__ __launch_bounds__(LPW *(L / E)) void k_z_r2c(const T *__restrict__ src, V2<T> *__restrict__ dst,
-                                                         long nlines, const V2<T> *__restrict__ tw, T scale) {
+                                                         long nlines, const V2<T> *__restrict__ twg, T scale) {
     using C = V2<T>;
     constexpr int TPL = L / E;
     constexpr int NT = LPW * TPL;
-    constexpr int LS = L + 1;
+    constexpr int LL = lds_line_len<L>();
     constexpr int NZH = L + 1;
-    __shared__ C lds[LPW * LS];
+    __shared__ C lds[LPW * LL];
+    __shared__ C tw[2 * L];
     const int tid = threadIdx.x;
-    const long l0 = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW;
-    const long avail = nlines - l0;
-    const C *s2 = reinterpret_cast<const C *>(src) + l0 * L;
-    for (int q = tid; q < LPW * L; q += NT) {
-        const int ln = q / L;
-        C v = (ln < avail) ? s2[q] : mk<T>(0, 0);
-        lds[ln * LS + (q - ln * L)] = v;
-    }
-    __syncthreads();
     const int ln = tid / TPL;
     const int jt = tid % TPL;
-    C *d = lds + ln * LS;
-    line_fft<T, L, E, 1, 2>(d, jt, tw);
-    // split: X[k] = 1/2 (Z[k] + conj Z[L-k]) - i/2 W_N^k (Z[k] - conj Z[L-k]),  X[L] = Re Z0 - Im Z0
-    if (ln < avail) {
-        C *o = dst + (l0 + ln) * NZH;
+    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const bool valid = l < nlines;
+    const C *s2 = reinterpret_cast<const C *>(src) + l * L;
+    C v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = valid ? s2[jt + i * TPL] : mk<T>(0, 0);
+    load_twiddles<T>(tw, twg, 2 * L, tid, NT);
+    __syncthreads();
+    C *d = lds + ln * LL;
+    line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+#pragma unroll
+    for (int i = 0; i < E; ++i) d[lds_at<1>(jt + i * TPL)] = v[i];
+    __syncthreads();
+    if (valid) {
+        C *o = dst + l * NZH;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
-            const C zk = d[k];
-            const C zm = cconj(d[(L - k) % L]);
+            const C zk = v[i];
+            const C zm = cconj(d[lds_at<1>((L - k) % L)]);
             const C a = cadd(zk, zm);
             const C b = cmul(tw[k], csub(zk, zm));
             C x;
-            x.x = (T)0.5 * (a.x + b.y);
-            x.y = (T)0.5 * (a.y - b.x);
-            x.x *= scale;
-            x.y *= scale;
+            x.x = (T)0.5 * (a.x + b.y) * scale;
+            x.y = (T)0.5 * (a.y - b.x) * scale;
             o[k] = x;
         }
-        if (jt == 0) {
-            const C z0 = d[0];
-            o[L] = mk<T>((z0.x - z0.y) * scale, (T)0);
-        }
+        if (jt == 0) o[L] = mk<T>((v[0].x - v[0].y) * scale, (T)0);
     }
 }
 
 template <typename T, int L, int E, int LPW>
 __global__ __launch_bounds__(LPW *(L / E)) void k_z_c2r(const V2<T> *__restrict__ src, T *__restrict__ dst,
-                                                         long nlines, const V2<T> *__restrict__ tw) {
+                                                         long nlines, const V2<T> *__restrict__ twg) {
     using C = V2<T>;
     constexpr int TPL = L / E;
     constexpr int NT = LPW * TPL;
-    constexpr int LS = L + 1;
+    constexpr int LL = lds_line_len<L>();
     constexpr int NZH = L + 1;
-    __shared__ C lds[LPW * LS];
+    __shared__ C lds[LPW * LL];
+    __shared__ C tw[2 * L];
     const int tid = threadIdx.x;
-    const long l0 = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW;
-    const long avail = nlines - l0;
-    const C *s = src + l0 * NZH;
-    for (int q = tid; q < LPW * NZH; q += NT) {
-        const int ln = q / NZH;
-        C v = (ln < avail) ? s[q] : mk<T>(0, 0);
-        lds[ln * LS + (q - ln * NZH)] = v;
-    }
-    __syncthreads();
     const int ln = tid / TPL;
     const int jt = tid % TPL;
-    C *d = lds + ln * LS;
-    // merge: Z'[k] = (X[k] + conj X[L-k]) + i conj(W_N^k) (X[k] - conj X[L-k]); only the real
-    // parts of X[0] and X[L] enter.  The inverse DFT is done as conj(DFT(conj .)).
-    C zr[E];
+    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const bool valid = l < nlines;
+    const C *s = src + (valid ? l : 0) * NZH;
+    C v[E];
+    load_twiddles<T>(tw, twg, 2 * L, tid, NT);
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = jt + i * TPL;
-        C xk = d[k];
-        C xm = cconj(d[L - k]);
+        C xk = valid ? s[k] : mk<T>(0, 0);
+        C xm = valid ? cconj(s[L - k]) : mk<T>(0, 0);
         if (k == 0) {
             xk.y = 0;
             xm.y = 0;
         }
         const C a = cadd(xk, xm);
         const C b = cmul(cconj(tw[k]), csub(xk, xm));
-        C z;
-        z.x = a.x - b.y;
-        z.y = a.y + b.x;
-        zr[i] = cconj(z);
+        v[i] = mk<T>(a.x - b.y, -(a.y + b.x));  // conj(Z')
     }
-    __syncthreads();
+    C *d = lds + ln * LL;
+    line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+    if (valid) {
+        C *o = reinterpret_cast<C *>(dst) + l * L;
 #pragma unroll
-    for (int i = 0; i < E; ++i) d[jt + i * TPL] = zr[i];
-    __syncthreads();
-    line_fft<T, L, E, 1, 2>(d, jt, tw);
-    C *o = reinterpret_cast<C *>(dst) + l0 * L;
-    for (int q = tid; q < LPW * L; q += NT) {
-        const int l = q / L;
-        if (l < avail) {
-            C v = lds[l * LS + (q - l * L)];
-            v.y = -v.y;
-            o[q] = v;
-        }
+        for (int i = 0; i < E; ++i) o[jt + i * TPL] = mk<T>(v[i].x, -v[i].y);
     }
 }
 
@@ -219,13 +213,28 @@ void launch_z_c2r(const ZArgs &a, hipStream_t s) {
 }
 
 // ---- tile-shape candidates ----------------------------------------------------------------------------
-// Strided pass: W columns per workgroup, NT = W L / E threads.  Candidate c (0, 1, 2) uses
-// W = Wb << c with Wb = max(4, 64 E / L), kept when NT <= 1024 and the tile fits 64 KB.
-constexpr int strided_Wb(int L, int E) { return (64 * E / L) > 4 ? (64 * E / L) : 4; }
-template <typename T> constexpr bool strided_ok(int L, int E, int W) {
-    return W * (L / E) <= 1024 && W * (L / E) >= 64 && (long)L * W * 2 * sizeof(T) <= 65536;
+// Strided pass candidate (ce, cn): E = default_E(L) << ce points per thread, NT = 256 << cn
+// threads, W = NT E / L columns; kept when W is a whole number and the LDS tile fits the 160 KB of a CU.
+template <typename T> constexpr int strided_lds(int L, int W) { return (L * (W + 1) + L) * 2 * (int)sizeof(T); }
+template <typename T> constexpr bool strided_cand_ok(int L, int ce, int cn) {
+    int E = default_E(L) << ce;
+    int NT = 256 << cn;
+    if (E > L || !rplan_ok(L, E)) return false;
+    if ((NT * E) % L != 0) return false;
+    int W = NT * E / L;
+    if (W < 1 || W * (L / E) != NT) return false;
+    return strided_lds<T>(L, W) <= 163840;
 }
-// Z pass: LPW lines per workgroup so that NT = LPW L / E is 256 threads (or one line).
-constexpr int z_LPW(int L, int E) { return (256 / (L / E)) > 1 ? (256 / (L / E)) : 1; }
+// Z pass candidate (ce, cn): E = default_E(N/2) << ce, NT = 256 << cn threads (or one line).
+template <typename T> constexpr bool z_cand_ok(int N, int ce, int cn) {
+    int L = N / 2;
+    int E = default_E(L) << ce;
+    if (E > L || !rplan_ok(L, E)) return false;
+    int TPL = L / E;
+    int NT = 256 << cn;
+    int LPW = NT / TPL;
+    if (LPW < 1 || LPW * TPL != NT) return false;
+    return (long)(LPW * (L + L / 32 + 1) + 2 * L) * 2 * (long)sizeof(T) <= 163840;
+}
 
 }  // namespace tk

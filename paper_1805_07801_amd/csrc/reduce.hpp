@@ -37,3 +37,10 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 }
 
 }  // namespace tk
+
+namespace tk {
+// num = sum (a_i - b_i)^2, den = sum b_i^2 over n real values.  Synchronises s.
+tk_status reduce_diff(const void *a, const void *b, long n, tk_dtype dt, double *num, double *den, hipStream_t s);
+// Fill n real values with a deterministic pseudo-random pattern in [-1, 1).
+tk_status fill_pattern(void *x, long n, tk_dtype dt, unsigned seed, hipStream_t s);
+}  // namespace tk

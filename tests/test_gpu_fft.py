@@ -93,3 +93,27 @@ def test_fft_1024_sampled(tk):
     back = plan.c2r(X)
     err = torch.linalg.vector_norm((back.view(-1) - x.view(-1)).double()) / torch.linalg.vector_norm(x.view(-1).double())
     assert err.item() <= 1e-5
+
+
+@pytest.mark.parametrize("n", [8, 12, 24, 48, 96, 192, 384, 768, 16, 32, 64, 128, 256, 512, 1024])
+def test_every_tile_candidate_matches_oracle(tk, n):
+    """The autotuner may only choose among candidates that all reproduce the oracle."""
+    import torch
+    shapes = {0: (8, 8, n), 1: (8, n, 8), 2: (n, 8, 8)}
+    try:
+        for p in range(3):
+            shape = shapes[p]
+            f = synth.gaussian_field((1,) + shape, n + p)
+            ref = offt.rfft3(f[0].astype(np.float64))
+            for (a, E) in tk.tile_candidates(n, torch.float32, p):
+                tk.tune_set(n, torch.float32, p, a, E)
+                plan = tk.FFT3D(*shape, dtype=torch.float32)
+                assert f"E={E}" in plan.describe(p)
+                X = plan.r2c(torch.from_numpy(f).cuda())
+                assert diag.rel_l2(X.cpu().numpy()[0], ref, shape[2]) <= TOL["f32"], (p, a, E)
+                back = plan.c2r(X).cpu().numpy()
+                assert diag.rel_l2(back, f) <= TOL["f32"], (p, a, E)
+                plan.close()
+            tk.tune_set(n, torch.float32, p, 0, 0)
+    finally:
+        tk.tune_clear()
