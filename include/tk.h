@@ -163,8 +163,8 @@ tk_status ns_step(tk_ns_t ns, void *uhat_inout, double dt, int nsteps, double *t
 
 /* FP64 diagnostics of state uhat: energy E = sum w 1/2|u^|^2, dissipation 2 nu sum w
  * 1/2 |k|^2 |u^|^2, shell spectrum E(s) for s < nshell (shell s: (2s-1)^2 <= 4|k|^2 <
- * (2s+1)^2; any pointer may be NULL), and max |k.u^|/(|k||u^|).  Synchronises stream.
- * Returns TK_ESTATE if the energy is not finite. */
+ * (2s+1)^2; any pointer may be NULL), and the divergence max_k |k.u^|/|k| relative to
+ * max_k |u^|.  Synchronises stream.  Returns TK_ESTATE if the energy is not finite. */
 tk_status ns_diagnostics(tk_ns_t ns, const void *uhat, double *energy, double *dissipation,
                          double *spectrum, int nshell, double *max_div, void *stream);
 

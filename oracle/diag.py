@@ -63,17 +63,16 @@ def spectrum(uhat, nshell=None):
 
 
 def max_divergence(uhat):
-    """max over modes with k != 0 and u^ != 0 of |k . u^| / (|k| |u^|)."""
+    """max_k |k . u^(k)| / |k|, relative to max_k |u^(k)| (k = 0 excluded from the
+    numerator).  Relative to the largest mode rather than mode by mode, so that modes
+    holding only round-off do not dominate."""
     n = uhat.shape[-3]
     kx, ky, kz = fft.wavenumbers(n)
     kd = np.abs(kx * uhat[0] + ky * uhat[1] + kz * uhat[2])
     kn = np.sqrt((kx * kx + ky * ky + kz * kz).astype(np.float64))
-    un = np.sqrt(np.sum(np.abs(uhat) ** 2, axis=0))
-    den = np.broadcast_to(kn, un.shape) * un
-    ok = den > 0
-    if not np.any(ok):
-        return 0.0
-    return float(np.max(np.where(ok, kd / np.where(ok, den, 1.0), 0.0)))
+    num = np.where(kn > 0, kd / np.where(kn > 0, kn, 1.0), 0.0)
+    umax = np.max(np.sqrt(np.sum(np.abs(uhat) ** 2, axis=0)))
+    return float(np.max(num) / umax) if umax > 0 else 0.0
 
 
 def parseval(f, F):

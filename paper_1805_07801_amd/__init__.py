@@ -22,6 +22,11 @@ class TkError(RuntimeError):
         self.status = status
 
 
+class NsConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("scheme", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
 def _declare(L):
     vp, i, u, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double, ctypes.c_size_t
     P = ctypes.POINTER
@@ -41,6 +46,13 @@ def _declare(L):
         "fft3d_tune_set": ([i, i, i, i, i], i),
         "fft3d_tune_clear": ([], i),
         "fft3d_tile_candidates": ([i, i, i, P(i), P(i), i], i),
+        "ns_create": ([P(vp), P(NsConfig)], i),
+        "ns_rhs": ([vp, vp, vp, vp], i),
+        "ns_step": ([vp, vp, d, i, P(d), vp], i),
+        "ns_diagnostics": ([vp, vp, P(d), P(d), P(d), i, P(d), vp], i),
+        "ns_init_random": ([vp, vp, vp, d, vp], i),
+        "ns_last_dt": ([vp, P(d)], i),
+        "ns_destroy": ([vp], i),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -209,6 +221,88 @@ class FFT3D:
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             lib().fft3d_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def num_shells(n):
+    """Shells 0..S-1 cover every stored mode: S = floor(sqrt(3) n / 2) + 2."""
+    return int(0.8660254037844386 * n) + 2
+
+
+class NS:
+    """Pseudo-spectral Navier-Stokes solver on an n^3 periodic grid (state u^ of shape
+    [3][n][n][n/2+1], complex, on the GPU)."""
+
+    def __init__(self, n, dtype=None, nu=0.0, cfl=0.0, scheme="rk2"):
+        import torch
+        dtype = dtype or torch.float32
+        self.n = n
+        self.dtype = dtype
+        self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
+        self.nu = nu
+        cfg = NsConfig(n, _dtype_code(dtype), float(nu), float(cfl), {"rk2": 0, "rk4": 1}[scheme], 0)
+        h = ctypes.c_void_p()
+        check(lib().ns_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self.h = h
+
+    def _check_state(self, t):
+        n = self.n
+        if t.dtype != self.cdtype or not t.is_cuda or not t.is_contiguous() or t.numel() != 3 * n * n * (n // 2 + 1):
+            raise TkError(TK_EINVAL, "state must be a contiguous %s GPU tensor [3][n][n][n/2+1]" % self.cdtype)
+
+    def empty_state(self):
+        import torch
+        n = self.n
+        return torch.zeros((3, n, n, n // 2 + 1), dtype=self.cdtype, device="cuda")
+
+    def rhs(self, u, out=None, stream=None):
+        self._check_state(u)
+        out = self.empty_state() if out is None else out
+        self._check_state(out)
+        check(lib().ns_rhs(self.h, _ptr(u), _ptr(out), _stream(stream)))
+        return out
+
+    def step(self, u, dt, nsteps=1, t=0.0, stream=None):
+        """Advance u in place; returns the new time."""
+        self._check_state(u)
+        tt = ctypes.c_double(t)
+        check(lib().ns_step(self.h, _ptr(u), float(dt), int(nsteps), ctypes.byref(tt), _stream(stream)))
+        return tt.value
+
+    def last_dt(self):
+        d = ctypes.c_double()
+        check(lib().ns_last_dt(self.h, ctypes.byref(d)))
+        return d.value
+
+    def diagnostics(self, u, nshell=None, stream=None):
+        self._check_state(u)
+        nshell = num_shells(self.n) if nshell is None else nshell
+        e, eps, md = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        spec = (ctypes.c_double * max(nshell, 1))()
+        check(lib().ns_diagnostics(self.h, _ptr(u), ctypes.byref(e), ctypes.byref(eps), spec, nshell,
+                                   ctypes.byref(md), _stream(stream)))
+        return {"energy": e.value, "dissipation": eps.value, "max_div": md.value,
+                "spectrum": [spec[i] for i in range(nshell)]}
+
+    def init_random(self, noise, energy=1.0, out=None, stream=None):
+        """Random solenoidal state from real noise [3][n][n][n] (see ns_init_random)."""
+        n = self.n
+        if noise.dtype != self.dtype or not noise.is_cuda or not noise.is_contiguous() or noise.numel() != 3 * n ** 3:
+            raise TkError(TK_EINVAL, "noise must be a contiguous %s GPU tensor [3][n][n][n]" % self.dtype)
+        out = self.empty_state() if out is None else out
+        self._check_state(out)
+        check(lib().ns_init_random(self.h, _ptr(noise), _ptr(out), float(energy), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().ns_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -25,6 +25,7 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",
+    "-Wno-unused-result",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

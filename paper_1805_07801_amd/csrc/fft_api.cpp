@@ -45,7 +45,7 @@ const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E) {
 
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
                        long SI, const void *tw, int inv, double scale, hipStream_t s) {
-    StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale};
+    StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale, -1, -1};
     k->fn(a, s);
     return launch_check("strided pass");
 }

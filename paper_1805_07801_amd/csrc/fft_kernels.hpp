@@ -25,6 +25,10 @@ struct StridedArgs {
     const void *tw;  // W_L^j table, L = line length
     int inv;         // 0: exp(-i..) forward; 1: exp(+i..) inverse
     double scale;    // applied on store
+    // Row masks (used by the 2/3-dealiased solver): with kl >= 0 only rows r with
+    // min(r, L - r) <= kl are read (the others are taken as zero); with ks >= 0 only such
+    // rows are written.  -1: every row.
+    int kl = -1, ks = -1;
 };
 using StridedFn = void (*)(const StridedArgs &, hipStream_t);
 
@@ -57,10 +61,12 @@ const std::vector<ZKernel> &z_kernels();
 // ---- strided complex pass ----------------------------------------------------------------------
 template <int L, int E, int W> constexpr int strided_es() { return W + 1; }
 
+__device__ __forceinline__ bool row_kept(int r, int L, int k) { return k < 0 || r <= k || r >= L - k; }
+
 template <typename T, int L, int E, int W>
 __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                          long SO, long SI, const V2<T> *__restrict__ twg,
-                                                         int inv, T scale) {
+                                                         int inv, T scale, int kl, int ks) {
     using C = V2<T>;
     constexpr int TPL = L / E;
     constexpr int NT = W * TPL;
@@ -76,7 +82,8 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> 
     C v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        C x = valid ? src[base + (long)(jt + i * TPL) * SI] : mk<T>(0, 0);
+        const int r = jt + i * TPL;
+        C x = (valid && row_kept(r, L, kl)) ? src[base + (long)r * SI] : mk<T>(0, 0);
         if (inv) x.y = -x.y;
         v[i] = x;
     }
@@ -86,11 +93,12 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> 
     if (valid) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
+            const int r = jt + i * TPL;
             C x = v[i];
             if (inv) x.y = -x.y;
             x.x *= scale;
             x.y *= scale;
-            dst[base + (long)(jt + i * TPL) * SI] = x;
+            if (row_kept(r, L, ks)) dst[base + (long)r * SI] = x;
         }
     }
 }
@@ -100,7 +108,7 @@ void launch_strided(const StridedArgs &a, hipStream_t s) {
     constexpr int NT = W * (L / E);
     unsigned nb = cdiv(a.ncols, W);
     hipLaunchKernelGGL((k_strided<T, L, E, W>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src, (V2<T> *)a.dst,
-                       a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale);
+                       a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl, a.ks);
 }
 
 // ---- Z pass: real lines <-> half spectra ----------------------------------------------------------

@@ -1,0 +1,279 @@
+// Navier-Stokes solver handle: workspace, right-hand sides, IF-RK2 / IF-RK4 steps (one
+// step captured once as a HIP graph and replayed), diagnostics and the random initial
+// field.  Paper, Section "Spectral Solver" (eq:NSk, eq:continuity2) and Section "Scaling
+// of Fluid spectral solver" (fourth-order Runge-Kutta, 2/3 rule, nine transforms per
+// right-hand side).
+#include <cmath>
+#include <mutex>
+#include <new>
+
+#include "ns_api.hpp"
+
+namespace tk {
+
+void register_ns_a(std::vector<NsKernels> &v);
+void register_ns_b(std::vector<NsKernels> &v);
+void register_ns_c(std::vector<NsKernels> &v);
+
+const std::vector<NsKernels> &ns_kernels() {
+    static std::vector<NsKernels> K;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_ns_a(K);
+        register_ns_b(K);
+        register_ns_c(K);
+    });
+    return K;
+}
+
+tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
+    TK_TRY(axes_init(&g->ax, n, n, n, dt, true));
+    g->n = n;
+    g->dt = dt;
+    g->K = (n - 1) / 3;
+    g->KZC = g->K + 1;
+    g->nk = nullptr;
+    for (const auto &k : ns_kernels())
+        if (k.N == n && k.dt == dt) g->nk = &k;
+    if (!g->nk) return fail(TK_EUNSUPPORTED, "no solver kernels for n=%d", n);
+    return TK_OK;
+}
+
+tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, unsigned *umax,
+                      NsState *st_set, hipStream_t s) {
+    const int n = g.n;
+    const long nzh = n / 2 + 1;
+    // P1: x-inverse of u^ and omega^ = i k x u^
+    g.nk->p1(uin, w6, g.K, g.KZC, g.ax.twx, s);
+    TK_TRY(launch_check("ns P1"));
+    // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
+    StridedArgs y2{w6, w6, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
+    g.ax.ky->fn(y2, s);
+    TK_TRY(launch_check("ns P2"));
+    // P3: z fused c2r -> u x omega -> r2c
+    g.nk->p3(w6, (long)n * n, g.KZC, g.ax.twz, umax, s);
+    TK_TRY(launch_check("ns P3"));
+    if (st_set) {
+        hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(64), 0, s, st_set);
+        TK_TRY(launch_check("ns step size"));
+    }
+    // P4: y-forward of the 3 products, kept ky rows written
+    StridedArgs y4{w6, w6, 3L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 0, 1.0, -1, g.K};
+    g.ax.ky->fn(y4, s);
+    TK_TRY(launch_check("ns P4"));
+    // P5: x-forward, projection, stage combine
+    P5Args a = p5;
+    a.c3 = w6;
+    g.nk->p5(a, g.K, g.KZC, g.ax.twx, s);
+    return launch_check("ns P5");
+}
+
+}  // namespace tk
+
+using namespace tk;
+
+struct tk_ns_s {
+    ns_config cfg;
+    NsGrid g;
+    size_t fbytes;  // one spectral field
+    void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
+    NsState *st = nullptr;
+    double *dscratch = nullptr;
+    int nshell = 0;
+    double last_dt = 0;
+    NsState hstage{};  // host staging copy of the step state (outlives async copies)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    void *graph_u = nullptr;
+};
+
+static void ns_free(tk_ns_s *p) {
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->w6) hipFree(p->w6);
+    if (p->aux) hipFree(p->aux);
+    if (p->ust) hipFree(p->ust);
+    if (p->st) hipFree(p->st);
+    if (p->dscratch) hipFree(p->dscratch);
+    delete p;
+}
+
+extern "C" tk_status ns_create(tk_ns_t *out, const ns_config *cfg) {
+    if (!out || !cfg) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (cfg->nu < 0 || !std::isfinite(cfg->nu)) return fail(TK_EINVAL, "nu must be finite and >= 0");
+    if (cfg->cfl < 0 || !std::isfinite(cfg->cfl)) return fail(TK_EINVAL, "cfl must be finite and >= 0");
+    if (cfg->scheme != 0 && cfg->scheme != 1) return fail(TK_EUNSUPPORTED, "scheme must be 0 (RK2) or 1 (RK4)");
+    if (!supported_len(cfg->n)) return fail(TK_EUNSUPPORTED, "unsupported n=%d", cfg->n);
+    tk_ns_s *p = new (std::nothrow) tk_ns_s();
+    if (!p) return fail(TK_ENOMEM, "host allocation failed");
+    p->cfg = *cfg;
+    tk_status st = ns_grid_init(&p->g, cfg->n, cfg->dtype);
+    if (st != TK_OK) {
+        delete p;
+        return st;
+    }
+    const int n = cfg->n;
+    p->fbytes = (size_t)n * n * (n / 2 + 1) * (cfg->dtype == TK_F32 ? 8 : 16);
+    p->nshell = ns_num_shells(n);
+    const size_t dbytes = sizeof(double) * ((size_t)(NS_DIAG_BLOCKS + 2) * (NS_DIAG_HEAD + p->nshell));
+    if (hipMalloc(&p->w6, 6 * p->fbytes) != hipSuccess || hipMalloc(&p->aux, 3 * p->fbytes) != hipSuccess ||
+        hipMalloc(&p->ust, 3 * p->fbytes) != hipSuccess || hipMalloc((void **)&p->st, sizeof(NsState)) != hipSuccess ||
+        hipMalloc((void **)&p->dscratch, dbytes) != hipSuccess) {
+        ns_free(p);
+        return fail(TK_ENOMEM, "solver workspace allocation (%zu bytes) failed", 12 * p->fbytes);
+    }
+    NsState h0{};
+    if (hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {
+        ns_free(p);
+        return fail(TK_EHIP, "state upload failed");
+    }
+    *out = p;
+    return TK_OK;
+}
+
+static tk_status ns_one_step(tk_ns_s *p, void *u, hipStream_t s) {
+    const NsGrid &g = p->g;
+    P5Args a{};
+    a.u = u;
+    a.aux = p->aux;
+    a.ust = p->ust;
+    a.st = p->st;
+    a.nu = p->cfg.nu;
+    if (p->cfg.scheme == 0) {
+        a.mode = RK2_S1;
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        a.mode = RK2_S2;
+        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+    } else {
+        a.mode = RK4_S1;
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        for (int m = RK4_S2; m <= RK4_S4; ++m) {
+            a.mode = m;
+            TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+        }
+    }
+    return TK_OK;
+}
+
+extern "C" tk_status ns_rhs(tk_ns_t p, const void *uhat, void *rhs_out, void *stream) {
+    if (!p || !uhat || !rhs_out) return fail(TK_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const long nvals = 3L * p->g.n * p->g.n * (p->g.n / 2 + 1);
+    if (p->cfg.dtype == TK_F32) hipLaunchKernelGGL(k_zero<float2>, dim3(4096), dim3(256), 0, s, (float2 *)rhs_out, nvals);
+    else hipLaunchKernelGGL(k_zero<double2>, dim3(4096), dim3(256), 0, s, (double2 *)rhs_out, nvals);
+    TK_TRY(launch_check("zero rhs"));
+    P5Args a{};
+    a.u = const_cast<void *>(uhat);
+    a.out = rhs_out;
+    a.st = p->st;
+    a.nu = p->cfg.nu;
+    a.mode = NS_RHS;
+    return ns_rhs_eval(p->g, uhat, p->w6, a, nullptr, nullptr, s);
+}
+
+extern "C" tk_status ns_step(tk_ns_t p, void *u, double dt, int nsteps, double *t_inout, void *stream) {
+    if (!p || !u) return fail(TK_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(TK_EINVAL, "nsteps must be >= 0");
+    if (p->cfg.cfl <= 0 && !(dt > 0 && std::isfinite(dt))) return fail(TK_EINVAL, "dt must be > 0 without CFL");
+    hipStream_t s = (hipStream_t)stream;
+    NsState &h0 = p->hstage;
+    h0 = NsState{};
+    h0.t = t_inout ? *t_inout : 0.0;
+    h0.hfix = dt > 0 ? dt : 0.0;
+    h0.cfl_dx = p->cfg.cfl > 0 ? p->cfg.cfl * 2.0 * M_PI / p->cfg.n : 0.0;
+    h0.h = h0.hfix;
+    TK_HIP_CHECK(hipMemcpyAsync(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+    if (nsteps > 0) {
+        // one step as a graph, captured once per state buffer and replayed
+        if (p->graph_u != u || !p->gexec) {
+            if (p->gexec) hipGraphExecDestroy(p->gexec);
+            if (p->graph) hipGraphDestroy(p->graph);
+            p->gexec = nullptr;
+            p->graph = nullptr;
+            p->graph_u = nullptr;
+            hipStream_t cs;
+            TK_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            TK_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            tk_status st = ns_one_step(p, u, cs);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &gr);
+            hipStreamDestroy(cs);
+            if (st != TK_OK) {
+                if (gr) hipGraphDestroy(gr);
+                return st;
+            }
+            if (e != hipSuccess) return fail(TK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&p->gexec, gr, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(gr);
+                return fail(TK_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            }
+            p->graph = gr;
+            p->graph_u = u;
+        }
+        for (int i = 0; i < nsteps; ++i) TK_HIP_CHECK(hipGraphLaunch(p->gexec, s));
+    }
+    NsState hf{};
+    TK_HIP_CHECK(hipMemcpyAsync(&hf, p->st, sizeof(hf), hipMemcpyDeviceToHost, s));
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    if (t_inout) *t_inout = hf.t;
+    p->last_dt = hf.h;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_last_dt(tk_ns_t p, double *dt) {
+    if (!p || !dt) return fail(TK_EINVAL, "NULL argument");
+    *dt = p->last_dt;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_diagnostics(tk_ns_t p, const void *u, double *energy, double *dissipation, double *spectrum,
+                                    int nshell, double *max_div, void *stream) {
+    if (!p || !u) return fail(TK_EINVAL, "NULL argument");
+    if (nshell < 0 || (nshell > 0 && !spectrum)) return fail(TK_EINVAL, "bad spectrum arguments");
+    std::vector<double> h(NS_DIAG_HEAD + p->nshell);
+    TK_TRY(ns_diag_run(u, p->g.n, p->cfg.dtype, p->nshell, p->dscratch, h.data(), (hipStream_t)stream));
+    if (energy) *energy = h[0];
+    if (dissipation) *dissipation = 2.0 * p->cfg.nu * h[1];
+    if (max_div) *max_div = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
+    for (int i = 0; i < nshell; ++i) spectrum[i] = i < p->nshell ? h[NS_DIAG_HEAD + i] : 0.0;
+    if (!std::isfinite(h[0])) return fail(TK_ESTATE, "energy is not finite");
+    return TK_OK;
+}
+
+extern "C" tk_status ns_init_random(tk_ns_t p, const void *noise, void *u, double energy, void *stream) {
+    if (!p || !noise || !u) return fail(TK_EINVAL, "NULL argument");
+    if (!(energy > 0) || !std::isfinite(energy)) return fail(TK_EINVAL, "energy must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const NsGrid &g = p->g;
+    const int n = g.n;
+    TK_TRY(fft_z_r2c(g.ax, noise, u, 3, 1.0, s));
+    TK_TRY(fft_y_pass(g.ax, u, u, 3, 0, s));
+    TK_TRY(fft_x_pass(g.ax, u, u, 3, 0, 1.0 / ((double)n * n * n), s));
+    TK_TRY(ns_init_project(u, n, g.dt, s));
+    std::vector<double> h(NS_DIAG_HEAD + p->nshell);
+    TK_TRY(ns_diag_run(u, n, g.dt, p->nshell, p->dscratch, h.data(), s));
+    std::vector<double> fac(p->nshell, 0.0);
+    double total = 0;
+    for (int sh = 1; sh < p->nshell; ++sh) {
+        const double es = h[NS_DIAG_HEAD + sh];
+        if (es > 0) {
+            const double et = std::pow((double)sh, 4) * std::exp(-2.0 * (sh / 4.0) * (sh / 4.0));
+            fac[sh] = std::sqrt(et / es);
+            total += et;
+        }
+    }
+    if (!(total > 0)) return fail(TK_ESTATE, "noise field has no energy in the kept shells");
+    const double g2 = std::sqrt(energy / total);
+    for (auto &f : fac) f *= g2;
+    TK_HIP_CHECK(hipMemcpyAsync(p->dscratch, fac.data(), sizeof(double) * p->nshell, hipMemcpyHostToDevice, s));
+    TK_TRY(ns_scale_shells(u, n, g.dt, p->dscratch, p->nshell, s));
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+extern "C" tk_status ns_destroy(tk_ns_t p) {
+    if (p) ns_free(p);
+    return TK_OK;
+}

@@ -1,0 +1,35 @@
+// Internal interface of the Navier-Stokes solver (shared by the single solver, the
+// ensemble and the LES).
+#pragma once
+
+#include "fft_api.hpp"
+#include "ns_kernels.hpp"
+
+namespace tk {
+
+constexpr int NS_DIAG_BLOCKS = 1024;
+constexpr int NS_DIAG_HEAD = 4;
+inline int ns_num_shells(int N) { return (int)(0.8660254037844386 * N) + 2; }
+
+// Diagnostics into hout[0..NS_DIAG_HEAD+nshell): energy, enstrophy, max |k.u^|^2/|k|^2,
+// max |u^|^2, E(s).
+tk_status ns_diag_run(const void *u, int N, tk_dtype dt, int nshell, double *dscratch, double *hout, hipStream_t s);
+tk_status ns_init_project(void *u, int N, tk_dtype dt, hipStream_t s);
+tk_status ns_scale_shells(void *u, int N, tk_dtype dt, const double *fac_dev, int nshell, hipStream_t s);
+
+// Everything one grid size needs to evaluate right-hand sides.
+struct NsGrid {
+    int n, K, KZC;
+    tk_dtype dt;
+    FftAxes ax;
+    const NsKernels *nk;
+};
+tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
+
+// One right-hand side of input uin (3 fields) through P1..P5 with workspace w6 (6 fields);
+// P5 combines according to `mode` (see NsMode).  umax != null: P3 records max |u|_1 and,
+// when st_set != null, the step-size kernel runs after P3.
+tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, unsigned *umax,
+                      NsState *st_set, hipStream_t s);
+
+}  // namespace tk

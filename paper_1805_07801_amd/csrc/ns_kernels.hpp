@@ -1,0 +1,412 @@
+// Kernels of the pseudo-spectral Navier-Stokes right-hand side and the integrating-factor
+// Runge-Kutta updates (paper, Section "Spectral Solver": eq:NSk with eq:continuity2,
+// nonlinear term pseudo-spectral, 2/3-rule dealiasing).
+//
+// One right-hand side is five passes over HBM:
+//   P1  X-inverse with the curl formed on load: u^ (3 fields) -> u^, omega^ = i k x u^
+//       (6 fields), transformed along x.
+//   P2  Y-inverse on the 6 fields (the generic strided kernel with row masks).
+//   P3  Z fused per line: 6 c2r -> c = u x omega (and max |u|_1 for the CFL step) ->
+//       3 r2c.  The real-space fields never reach HBM.
+//   P4  Y-forward on the 3 fields (generic strided kernel).
+//   P5  X-forward with the epilogue: 1/N^3, 2/3 mask, projection P = I - k k^T/|k|^2,
+//       then the integrating-factor Runge-Kutta stage combine.
+// Every pass touches only what the 2/3 rule keeps: with K = (N-1)/3 a mode survives iff
+// |kx|, |ky| <= K and kz <= K; columns and rows that only ever hold masked modes are
+// neither read nor written (their values are exact zeros in the unpruned computation).
+#pragma once
+
+#include "fft_kernels.hpp"
+
+namespace tk {
+
+// Stage-combine modes of P5.  h and the factors E = exp(-nu |k|^2 h), E2 = exp(-nu|k|^2 h/2)
+// come from the device step state; N is the projected, masked nonlinear term.
+enum NsMode : int {
+    NS_RHS = 0,   // out = N
+    RK2_S1 = 1,   // aux = N ;           ust = E (u + h N)
+    RK2_S2 = 2,   // u = E u + h/2 (E aux + N)
+    RK4_S1 = 3,   // aux = E N ;         ust = E2 (u + h/2 N)
+    RK4_S2 = 4,   // aux += 2 E2 N ;     ust = E2 u + h/2 N
+    RK4_S3 = 5,   // aux += 2 E2 N ;     ust = E u + h E2 N
+    RK4_S4 = 6    // u = E u + h/6 (aux + N)
+};
+
+// Device step state.
+struct NsState {
+    double h;        // current step size
+    double t;        // time (advanced by h at the start of each step)
+    unsigned umax;   // max over grid of |ux| + |uy| + |uz| (float bits), for the CFL step
+    unsigned pad;
+    double cfl_dx;   // cfl * 2 pi / N (0: fixed step)
+    double hfix;     // fixed step size
+};
+
+__device__ __forceinline__ int wave_k(int r, int L) { return r < L / 2 ? r : r - L; }
+// Odd (first-derivative) wavenumber: Nyquist taken as zero.
+__device__ __forceinline__ int deriv_k(int r, int L) { return (2 * r == L) ? 0 : wave_k(r, L); }
+
+// Column cc of the kept (ky, kz) set: kyi = cc / KZC, kz = cc % KZC; ky index kyi for
+// kyi <= K, else kyi + N - 2K - 1 (the negative wavenumbers).  Returns the offset of the
+// column inside one field plane row (ky_row * NZH + kz) and the two wavenumbers.
+__device__ __forceinline__ long kept_col(long cc, int N, int K, int KZC, int NZH, int *ky, int *kz) {
+    int kyi = (int)(cc / KZC);
+    *kz = (int)(cc - (long)kyi * KZC);
+    int row = kyi <= K ? kyi : kyi + N - 2 * K - 1;
+    *ky = wave_k(row, N);
+    return (long)row * NZH + *kz;
+}
+
+// ---- P1: X-inverse with curl on load -------------------------------------------------------------
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
+                                                       int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    constexpr int N = L;
+    constexpr int NZH = N / 2 + 1;
+    constexpr int TPL = L / E;
+    constexpr int NT = W * TPL;
+    constexpr int ES = W + 1;
+    constexpr long FS = (long)N * N * NZH;  // field stride
+    constexpr long RS = (long)N * NZH;      // x-row stride
+    __shared__ C lds[L * ES];
+    __shared__ C tw[L];
+    const int tid = threadIdx.x;
+    const int col = tid % W;
+    const int jt = tid / W;
+    const long ncols = (long)(2 * K + 1) * KZC;
+    const long cc = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
+    const bool valid = cc < ncols;
+    int ky = 0, kz = 0;
+    const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    const int kyd = ky, kzd = (2 * kz == N) ? 0 : kz;
+    C a0[E], a1[E], a2[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int r = jt + i * TPL;
+        const bool ld = valid && row_kept(r, L, K);
+        const long o = (long)r * RS + j;
+        a0[i] = ld ? u[o] : mk<T>(0, 0);
+        a1[i] = ld ? u[FS + o] : mk<T>(0, 0);
+        a2[i] = ld ? u[2 * FS + o] : mk<T>(0, 0);
+    }
+    load_twiddles<T>(tw, twg, L, tid, NT);
+    __syncthreads();
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int kx = deriv_k(jt + i * TPL, N);
+            C x;
+            if (f == 0) x = a0[i];
+            else if (f == 1) x = a1[i];
+            else if (f == 2) x = a2[i];
+            else {
+                // omega = i k x u
+                C b;
+                if (f == 3) b = csub(cscale(a2[i], (T)kyd), cscale(a1[i], (T)kzd));
+                else if (f == 4) b = csub(cscale(a0[i], (T)kzd), cscale(a2[i], (T)kx));
+                else b = csub(cscale(a1[i], (T)kx), cscale(a0[i], (T)kyd));
+                x = cmul_pi(b);
+            }
+            v[i] = cconj(x);  // inverse transform as conj(DFT(conj .))
+        }
+        line_fft<T, L, E, ES>(v, lds + col, jt, tw);
+        if (valid) {
+            V2<T> *dst = w6 + f * FS + j;
+#pragma unroll
+            for (int i = 0; i < E; ++i) dst[(long)(jt + i * TPL) * RS] = cconj(v[i]);
+        }
+    }
+}
+
+// ---- P3: fused Z pass ------------------------------------------------------------------------------
+// Lines l = x * N + y of the 6 fields in w6 (kz < KZC nonzero); outputs c = u x omega
+// transformed back, kz < KZC, into fields 0..2 of w6 (in place: each workgroup reads all
+// six fields of its lines before it writes).
+template <typename T, int L, int E, int LPW>
+__global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, int KZC,
+                                                         const V2<T> *__restrict__ twg, unsigned *umax) {
+    using C = V2<T>;
+    constexpr int N = 2 * L;
+    constexpr int NZH = L + 1;
+    constexpr int TPL = L / E;
+    constexpr int NT = LPW * TPL;
+    constexpr int LL = lds_line_len<L>();
+    constexpr long FS = (long)N * N * NZH;
+    __shared__ C lds[LPW * LL];
+    __shared__ C tw[2 * L];
+    const int tid = threadIdx.x;
+    const int ln = tid / TPL;
+    const int jt = tid % TPL;
+    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const bool valid = l < nlines;
+    C *d = lds + ln * LL;
+    load_twiddles<T>(tw, twg, 2 * L, tid, NT);
+    __syncthreads();
+    // real-space samples: r[f][i] = (x[2n], x[2n+1]) at n = jt + i TPL
+    C r[6][E];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const C *s = w6 + f * FS + (valid ? l : 0) * NZH;
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int k = jt + i * TPL;
+            C xk = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
+            C xm = (valid && L - k < KZC) ? cconj(s[L - k]) : mk<T>(0, 0);
+            if (k == 0) {
+                xk.y = 0;
+                xm.y = 0;
+            }
+            const C a = cadd(xk, xm);
+            const C b = cmul(cconj(tw[k]), csub(xk, xm));
+            v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
+        }
+        line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) r[f][i] = mk<T>(v[i].x, -v[i].y);
+    }
+    // c = u x omega, both samples of each packed pair; CFL maximum of |u|_1
+    float m = 0.f;
+    C c[3][E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const C ux = r[0][i], uy = r[1][i], uz = r[2][i], wx = r[3][i], wy = r[4][i], wz = r[5][i];
+        c[0][i] = mk<T>(uy.x * wz.x - uz.x * wy.x, uy.y * wz.y - uz.y * wy.y);
+        c[1][i] = mk<T>(uz.x * wx.x - ux.x * wz.x, uz.y * wx.y - ux.y * wz.y);
+        c[2][i] = mk<T>(ux.x * wy.x - uy.x * wx.x, ux.y * wy.y - uy.y * wx.y);
+        const float s0 = (float)(fabs(ux.x) + fabs(uy.x) + fabs(uz.x));
+        const float s1 = (float)(fabs(ux.y) + fabs(uy.y) + fabs(uz.y));
+        m = fmaxf(m, fmaxf(s0, s1));
+    }
+    if (umax) {
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if ((tid & 63) == 0 && valid) atomicMax(umax, __float_as_uint(m));
+    }
+    // forward r2c of the three products (unscaled; P5 applies 1/N^3)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = c[f][i];
+        line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) d[lds_at<1>(jt + i * TPL)] = v[i];
+        __syncthreads();
+        if (valid) {
+            C *o = w6 + f * FS + l * NZH;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int k = jt + i * TPL;
+                if (k < KZC) {
+                    const C zk = v[i];
+                    const C zm = cconj(d[lds_at<1>((L - k) % L)]);
+                    const C a = cadd(zk, zm);
+                    const C b = cmul(tw[k], csub(zk, zm));
+                    o[k] = mk<T>((T)0.5 * (a.x + b.y), (T)0.5 * (a.y - b.x));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
+struct P5Args {
+    const void *c3;    // 3 fields after P4
+    const void *add3;  // optional extra term added before masking/projection (spectral, scaled), or null
+    void *u;           // state (read; written by RK2_S2 / RK4_S4)
+    void *aux;         // RK2: N^n; RK4: accumulator
+    void *ust;         // stage input written by the first stages
+    void *out;         // NS_RHS output
+    const NsState *st;
+    double nu;
+    int mode;
+};
+
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3,
+                                                       V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
+                                                       const NsState *__restrict__ st, double nu, int mode, int K,
+                                                       int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    constexpr int N = L;
+    constexpr int NZH = N / 2 + 1;
+    constexpr int TPL = L / E;
+    constexpr int NT = W * TPL;
+    constexpr int ES = W + 1;
+    constexpr long FS = (long)N * N * NZH;
+    constexpr long RS = (long)N * NZH;
+    __shared__ C lds[L * ES];
+    __shared__ C tw[L];
+    const int tid = threadIdx.x;
+    const int col = tid % W;
+    const int jt = tid / W;
+    const long ncols = (long)(2 * K + 1) * KZC;
+    const long cc = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
+    const bool valid = cc < ncols;
+    int ky = 0, kz = 0;
+    const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    load_twiddles<T>(tw, twg, L, tid, NT);
+    C cf[3][E];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) cf[f][i] = valid ? c3[f * FS + (long)(jt + i * TPL) * RS + j] : mk<T>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cf[f][i];
+        line_fft<T, L, E, ES>(v, lds + col, jt, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) cf[f][i] = v[i];
+    }
+    if (!valid) return;
+    const T scale = (T)(1.0 / ((double)N * N * N));
+    const double h = st->h;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int r = jt + i * TPL;
+        if (!row_kept(r, L, K)) continue;
+        const int kx = wave_k(r, N);
+        const long o = (long)r * RS + j;
+        C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cscale(cf[2][i], scale);
+        if (add3) {
+            n0 = cadd(n0, add3[o]);
+            n1 = cadd(n1, add3[FS + o]);
+            n2 = cadd(n2, add3[2 * FS + o]);
+        }
+        const T k2 = (T)(kx * kx + ky * ky + kz * kz);
+        if (k2 > 0) {
+            const T ik2 = (T)1 / k2;
+            const C kd = cadd(cadd(cscale(n0, (T)kx), cscale(n1, (T)ky)), cscale(n2, (T)kz));
+            n0 = csub(n0, cscale(kd, (T)kx * ik2));
+            n1 = csub(n1, cscale(kd, (T)ky * ik2));
+            n2 = csub(n2, cscale(kd, (T)kz * ik2));
+        } else {
+            n0 = n1 = n2 = mk<T>(0, 0);
+        }
+        const C nn[3] = {n0, n1, n2};
+        if (mode == NS_RHS) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) out[f * FS + o] = nn[f];
+            continue;
+        }
+        const double a = nu * (double)k2 * h;
+        const T e1 = (T)exp(-a);
+        const T e2 = (T)exp(-0.5 * a);
+        const T th = (T)h;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const long q = f * FS + o;
+            const C uu = u[q];
+            const C n = nn[f];
+            switch (mode) {
+            case RK2_S1:
+                aux[q] = n;
+                ust[q] = cscale(cadd(uu, cscale(n, th)), e1);
+                break;
+            case RK2_S2:
+                u[q] = cadd(cscale(uu, e1), cscale(cadd(cscale(aux[q], e1), n), (T)0.5 * th));
+                break;
+            case RK4_S1:
+                aux[q] = cscale(n, e1);
+                ust[q] = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
+                break;
+            case RK4_S2:
+                aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
+                ust[q] = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
+                break;
+            case RK4_S3:
+                aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
+                ust[q] = cadd(cscale(uu, e1), cscale(n, th * e2));
+                break;
+            default:  // RK4_S4
+                u[q] = cadd(cscale(uu, e1), cscale(cadd(aux[q], n), th / (T)6));
+                break;
+            }
+        }
+    }
+}
+
+// ---- small kernels --------------------------------------------------------------------------------
+// CFL step size from the maximum P3 recorded (or the fixed step); advances t; clears umax.
+static __global__ void k_ns_set_h(NsState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double h = st->hfix;
+        if (st->cfl_dx > 0) {
+            const double um = (double)__uint_as_float(st->umax);
+            h = um > 0 ? st->cfl_dx / um : st->hfix;
+        }
+        st->h = h;
+        st->t += h;
+        st->umax = 0u;
+    }
+}
+
+template <typename C> __global__ void k_zero(C *p, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        C z;
+        z.x = 0;
+        z.y = 0;
+        p[i] = z;
+    }
+}
+
+// ---- instantiation helpers --------------------------------------------------------------------------
+// Tile shapes: P1/P5 use E = default_E(N) and W = 16 columns (8 for FP64 or when the
+// per-thread register arrays would be too large), P3 uses E = default_E(N/2), 256 threads.
+template <typename T> constexpr int ns_x_W(int N) {
+    int E = default_E(N);
+    int W = sizeof(T) == 8 ? 8 : 16;
+    while (W > 1 && W * (N / E) > 1024) W /= 2;
+    while (W * (N / E) < 64) W *= 2;
+    return W;
+}
+constexpr int ns_z_LPW(int N) {
+    int L = N / 2, E = default_E(L), TPL = L / E;
+    return TPL >= 256 ? 1 : 256 / TPL;
+}
+
+struct NsKernels {
+    int N;
+    tk_dtype dt;
+    void (*p1)(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s);
+    void (*p3)(void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s);
+    void (*p5)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
+};
+const std::vector<NsKernels> &ns_kernels();
+
+template <typename T, int N> NsKernels make_ns_kernels() {
+    constexpr int E = default_E(N);
+    constexpr int W = ns_x_W<T>(N);
+    constexpr int L2 = N / 2;
+    constexpr int E2 = default_E(L2);
+    constexpr int LPW = ns_z_LPW(N);
+    NsKernels k;
+    k.N = N;
+    k.dt = sizeof(T) == 4 ? TK_F32 : TK_F64;
+    k.p1 = [](const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
+        const long ncols = (long)(2 * K + 1) * KZC;
+        hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+                           (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw);
+    };
+    k.p3 = [](void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s) {
+        hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
+                           (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, umax);
+    };
+    k.p5 = [](const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
+        const long ncols = (long)(2 * K + 1) * KZC;
+        hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+                           (const V2<T> *)a.c3, (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux,
+                           (V2<T> *)a.ust, (V2<T> *)a.out, a.st, a.nu, a.mode, K, KZC, (const V2<T> *)tw);
+    };
+    return k;
+}
+
+}  // namespace tk

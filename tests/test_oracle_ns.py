@@ -218,3 +218,14 @@ def test_cfl_dt_taylor_green():
     n = 32
     h = ns.cfl_dt(tg_state(n), 0.5)
     assert abs(h - 0.5 * (2 * np.pi / n) / 1.0) <= 1e-14
+
+
+def test_max_divergence_closed_forms():
+    """u = (sin x, 0, 0) is a pure compression mode: |k.u^|/|k| = |u^| at k = (+-1,0,0), so
+    the relative divergence is 1; Taylor-Green is solenoidal (0 to round-off)."""
+    n = 16
+    X, Y, Z = grid3(n)
+    u = np.stack([np.sin(X + 0 * Y + 0 * Z), np.zeros((n, n, n)), np.zeros((n, n, n))])
+    assert abs(diag.max_divergence(fft.rfft3(u)) - 1.0) <= 1e-14
+    assert diag.max_divergence(tg_state(n)) <= 1e-15
+    assert diag.max_divergence(np.zeros((3, n, n, n // 2 + 1), complex)) == 0.0
