@@ -179,6 +179,36 @@ tk_status ns_last_dt(tk_ns_t ns, double *dt);
 
 tk_status ns_destroy(tk_ns_t ns);
 
+/* ------------------------------------------------------------------------------------
+ * Ensembles: `count` independent FP32 solves of mixed grid sizes n[i] in {16, 24, 32,
+ * 48, 64, 96, 128} with viscosities nu[i], advanced together by IF-RK2.  Every pass of
+ * the right-hand side is one persistent kernel over a work list of all members' tiles
+ * (largest grids first), and one step of all members is a single HIP-graph launch.
+ * Each member's state has the single solver's layout.  flags >> 16, if nonzero, sets
+ * the persistent grid size (workgroups; default 1024).
+ * ------------------------------------------------------------------------------------ */
+tk_status ns_batch_create(tk_nsb_t *b, int count, const int *n, const double *nu, tk_dtype dt, double cfl,
+                          unsigned flags);
+
+/* Advance every member by nsteps steps.  uhat: host array of `count` device pointers
+ * (member states, in place).  With cfl > 0 each member's step is from its own CFL
+ * condition, else h = dt.  t (host, count values, may be NULL) is advanced.
+ * Synchronises the stream at the end. */
+tk_status ns_batch_step(tk_nsb_t b, void *const *uhat, double dt, int nsteps, double *t, void *stream);
+
+/* Member i's random initial state (as ns_init_random).  Synchronises. */
+tk_status ns_batch_init_random(tk_nsb_t b, int i, const void *noise, void *uhat_out, double energy,
+                               void *stream);
+
+/* Member i's energy, dissipation and relative divergence (as ns_diagnostics). */
+tk_status ns_batch_diagnostics(tk_nsb_t b, int i, const void *uhat, double *energy, double *dissipation,
+                               double *max_div, void *stream);
+
+/* Step sizes of the last step of every member (host array of count values). */
+tk_status ns_batch_last_dt(tk_nsb_t b, double *dt);
+
+tk_status ns_batch_destroy(tk_nsb_t b);
+
 #ifdef __cplusplus
 }
 #endif

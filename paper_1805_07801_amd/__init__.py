@@ -53,6 +53,12 @@ def _declare(L):
         "ns_init_random": ([vp, vp, vp, d, vp], i),
         "ns_last_dt": ([vp, P(d)], i),
         "ns_destroy": ([vp], i),
+        "ns_batch_create": ([P(vp), i, P(i), P(d), i, d, u], i),
+        "ns_batch_step": ([vp, P(vp), d, i, P(d), vp], i),
+        "ns_batch_init_random": ([vp, i, vp, vp, d, vp], i),
+        "ns_batch_diagnostics": ([vp, i, vp, P(d), P(d), P(d), vp], i),
+        "ns_batch_last_dt": ([vp, P(d)], i),
+        "ns_batch_destroy": ([vp], i),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -303,6 +309,70 @@ class NS:
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             lib().ns_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Independent FP32 solves of mixed grid sizes advanced together (ns_batch_*): one
+    persistent kernel per pass over all members, one HIP-graph launch per step."""
+
+    def __init__(self, sizes, nus, cfl=0.0, grid=0):
+        import torch
+        self.sizes = list(sizes)
+        self.count = len(self.sizes)
+        n = (ctypes.c_int * self.count)(*self.sizes)
+        nu = (ctypes.c_double * self.count)(*[float(v) for v in nus])
+        self.nus = [float(v) for v in nus]
+        h = ctypes.c_void_p()
+        check(lib().ns_batch_create(ctypes.byref(h), self.count, n, nu, TK_F32, float(cfl), int(grid) << 16))
+        self.h = h
+        self.t = [0.0] * self.count
+
+    def empty_state(self, i):
+        import torch
+        n = self.sizes[i]
+        return torch.zeros((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+
+    def init_random(self, i, noise, energy=1.0, out=None, stream=None):
+        out = self.empty_state(i) if out is None else out
+        check(lib().ns_batch_init_random(self.h, i, _ptr(noise), _ptr(out), float(energy), _stream(stream)))
+        return out
+
+    def step(self, states, dt=0.0, nsteps=1, stream=None):
+        """Advance every member state (list of tensors) in place; returns member times."""
+        import torch
+        if len(states) != self.count:
+            raise TkError(TK_EINVAL, "need %d states" % self.count)
+        for i, u in enumerate(states):
+            n = self.sizes[i]
+            if u.dtype != torch.complex64 or not u.is_cuda or not u.is_contiguous() or u.numel() != 3 * n * n * (n // 2 + 1):
+                raise TkError(TK_EINVAL, "member %d state has the wrong shape/dtype" % i)
+        ptrs = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in states])
+        t = (ctypes.c_double * self.count)(*self.t)
+        check(lib().ns_batch_step(self.h, ptrs, float(dt), int(nsteps), t, _stream(stream)))
+        self.t = list(t)
+        return self.t
+
+    def last_dt(self):
+        d = (ctypes.c_double * self.count)()
+        check(lib().ns_batch_last_dt(self.h, d))
+        return list(d)
+
+    def diagnostics(self, i, u, stream=None):
+        e, eps, md = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().ns_batch_diagnostics(self.h, i, _ptr(u), ctypes.byref(e), ctypes.byref(eps), ctypes.byref(md),
+                                         _stream(stream)))
+        return {"energy": e.value, "dissipation": eps.value, "max_div": md.value}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().ns_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

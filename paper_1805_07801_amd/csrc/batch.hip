@@ -1,0 +1,407 @@
+// Ensembles of independent Navier-Stokes solves of mixed grid sizes.
+//
+// Each pass of a right-hand side (P1 .. P5, see ns_kernels.hpp) is ONE persistent kernel
+// for the whole ensemble: a grid sized to the GPU walks a work list of (instance, tile)
+// items, largest grids first, and dispatches on the item's grid size to the same tile
+// functions the single solver uses.  One IF-RK2 step of all members is captured once as
+// a HIP graph (eleven kernels) and replayed, so a step costs one graph launch.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "ns_api.hpp"
+
+namespace tk {
+
+#define TK_BATCH_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+constexpr int BNT = 256;  // threads per workgroup of every batch kernel
+
+// Tile shapes with 256 threads for every size: strided / X passes W = 256 E / N columns,
+// fused Z pass LPW = 256 / (N/2 / E2) lines.
+template <int N> struct BCfg {
+    static constexpr int E = default_E(N);
+    static constexpr int W = BNT * E / N;
+    static constexpr int L2 = N / 2;
+    static constexpr int E2 = default_E(L2);
+    static constexpr int LPW = BNT / (L2 / E2);
+    static constexpr int lds_x = N * (W + 1) + N;                      // exchange + twiddles
+    static constexpr int lds_z = LPW * lds_line_len<L2>() + N;         // lines + twiddles
+    static_assert(W * (N / E) == BNT && LPW * (L2 / E2) == BNT, "batch tile shape");
+};
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+template <int... Ns> constexpr int batch_lds_max() {
+    int m = 0;
+    ((m = cmax(m, cmax(BCfg<Ns>::lds_x, BCfg<Ns>::lds_z))), ...);
+    return m;
+}
+#define TK_LIST(N) N,
+constexpr int BLDS = batch_lds_max<TK_BATCH_SIZES(TK_LIST) 16>();
+#undef TK_LIST
+
+struct BInst {
+    int n, K, KZC, pad;
+    float2 *u, *w6, *aux, *ust;
+    NsState *st;
+    const float2 *tw;
+    double nu;
+};
+
+struct BItem {
+    int inst, tile;
+};
+
+static bool batch_size_ok(int n) {
+#define TK_OK_N(N) if (n == N) return true;
+    TK_BATCH_SIZES(TK_OK_N)
+#undef TK_OK_N
+    return false;
+}
+
+// ---- persistent pass kernels -------------------------------------------------------------------
+__global__ __launch_bounds__(BNT) void kb_p1(const BInst *__restrict__ inst, const BItem *__restrict__ items,
+                                             int nitems, int stage2) {
+    __shared__ float2 smem[BLDS];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem w = items[it];
+        const BInst &d = inst[w.inst];
+        const float2 *in = stage2 ? d.ust : d.u;
+        __syncthreads();
+        switch (d.n) {
+#define TK_CASE(N)                                                                                        \
+    case N: {                                                                                             \
+        float2 *tw = smem;                                                                                \
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
+        __syncthreads();                                                                                  \
+        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, d.KZC, w.tile, smem + N, tw);         \
+    } break;
+            TK_BATCH_SIZES(TK_CASE)
+#undef TK_CASE
+        }
+    }
+}
+
+__global__ __launch_bounds__(BNT) void kb_y(const BInst *__restrict__ inst, const BItem *__restrict__ items,
+                                            int nitems, int nf, int inv) {
+    __shared__ float2 smem[BLDS];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem w = items[it];
+        const BInst &d = inst[w.inst];
+        __syncthreads();
+        switch (d.n) {
+#define TK_CASE(N)                                                                                        \
+    case N: {                                                                                             \
+        float2 *tw = smem;                                                                                \
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
+        __syncthreads();                                                                                  \
+        constexpr long NZH = N / 2 + 1;                                                                   \
+        strided_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, d.w6, (long)nf * N * d.KZC, d.KZC, N * NZH,  \
+                                                       NZH, inv, 1.0f, inv ? d.K : -1, inv ? -1 : d.K,    \
+                                                       w.tile, smem + N, tw);                             \
+    } break;
+            TK_BATCH_SIZES(TK_CASE)
+#undef TK_CASE
+        }
+    }
+}
+
+__global__ __launch_bounds__(BNT) void kb_p3(const BInst *__restrict__ inst, const BItem *__restrict__ items,
+                                             int nitems, int with_umax) {
+    __shared__ float2 smem[BLDS];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem w = items[it];
+        const BInst &d = inst[w.inst];
+        unsigned *um = with_umax ? &d.st->umax : nullptr;
+        __syncthreads();
+        switch (d.n) {
+#define TK_CASE(N)                                                                                        \
+    case N: {                                                                                             \
+        float2 *tw = smem;                                                                                \
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
+        __syncthreads();                                                                                  \
+        ns_p3_tile<float, N / 2, BCfg<N>::E2, BCfg<N>::LPW>(d.w6, (long)N * N, d.KZC, w.tile, smem + N,   \
+                                                            tw, um);                                      \
+    } break;
+            TK_BATCH_SIZES(TK_CASE)
+#undef TK_CASE
+        }
+    }
+}
+
+__global__ __launch_bounds__(BNT) void kb_p5(const BInst *__restrict__ inst, const BItem *__restrict__ items,
+                                             int nitems, int mode) {
+    __shared__ float2 smem[BLDS];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem w = items[it];
+        const BInst &d = inst[w.inst];
+        __syncthreads();
+        switch (d.n) {
+#define TK_CASE(N)                                                                                        \
+    case N: {                                                                                             \
+        float2 *tw = smem;                                                                                \
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
+        __syncthreads();                                                                                  \
+        ns_p5_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, nullptr, d.u, d.aux, d.ust, nullptr, d.st,     \
+                                                     d.nu, mode, d.K, d.KZC, w.tile, smem + N, tw);       \
+    } break;
+            TK_BATCH_SIZES(TK_CASE)
+#undef TK_CASE
+        }
+    }
+}
+
+__global__ void kb_set_h(const BInst *__restrict__ inst, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        NsState *st = inst[i].st;
+        double h = st->hfix;
+        if (st->cfl_dx > 0) {
+            const double um = (double)__uint_as_float(st->umax);
+            h = um > 0 ? st->cfl_dx / um : st->hfix;
+        }
+        st->h = h;
+        st->t += h;
+        st->umax = 0u;
+    }
+}
+
+// Tiles per instance of each pass.
+static long tiles_x(int n, int K, int KZC) {
+    long W = 0;
+#define TK_W(N) if (n == N) W = BCfg<N>::W;
+    TK_BATCH_SIZES(TK_W)
+#undef TK_W
+    return ((long)(2 * K + 1) * KZC + W - 1) / W;
+}
+static long tiles_y(int n, int KZC, int nf) {
+    long W = 0;
+#define TK_W(N) if (n == N) W = BCfg<N>::W;
+    TK_BATCH_SIZES(TK_W)
+#undef TK_W
+    return ((long)nf * n * KZC + W - 1) / W;
+}
+static long tiles_z(int n) {
+    long LPW = 0;
+#define TK_W(N) if (n == N) LPW = BCfg<N>::LPW;
+    TK_BATCH_SIZES(TK_W)
+#undef TK_W
+    return ((long)n * n + LPW - 1) / LPW;
+}
+
+}  // namespace tk
+
+using namespace tk;
+
+struct tk_nsb_s {
+    int count = 0;
+    int grid = 1024;
+    std::vector<int> n;
+    std::vector<double> nu;
+    double cfl = 0;
+    std::vector<BInst> hinst;
+    BInst *dinst = nullptr;
+    std::vector<NsState> hstate;
+    NsState *dstate = nullptr;
+    // work lists: 0 = P1/P5, 1 = Y over 6 fields, 2 = Z lines, 3 = Y over 3 fields
+    BItem *items[4] = {nullptr, nullptr, nullptr, nullptr};
+    int nitems[4] = {0, 0, 0, 0};
+    std::vector<void *> bufs;
+    double *dscratch = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<NsGrid> grids;  // per instance (for init and diagnostics)
+};
+
+static void nsb_free(tk_nsb_s *b) {
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (void *p : b->bufs) hipFree(p);
+    for (auto &it : b->items)
+        if (it) hipFree(it);
+    if (b->dinst) hipFree(b->dinst);
+    if (b->dstate) hipFree(b->dstate);
+    if (b->dscratch) hipFree(b->dscratch);
+    delete b;
+}
+
+static tk_status nsb_capture(tk_nsb_s *b) {
+    hipStream_t cs;
+    TK_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    TK_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, b->nitems[list])); };
+    for (int stage = 0; stage < 2; ++stage) {
+        hipLaunchKernelGGL(kb_p1, dim3(g(0)), dim3(BNT), 0, cs, b->dinst, b->items[0], b->nitems[0], stage);
+        hipLaunchKernelGGL(kb_y, dim3(g(1)), dim3(BNT), 0, cs, b->dinst, b->items[1], b->nitems[1], 6, 1);
+        hipLaunchKernelGGL(kb_p3, dim3(g(2)), dim3(BNT), 0, cs, b->dinst, b->items[2], b->nitems[2], stage == 0);
+        if (stage == 0)
+            hipLaunchKernelGGL(kb_set_h, dim3(cdiv(b->count, 64)), dim3(64), 0, cs, b->dinst, b->count);
+        hipLaunchKernelGGL(kb_y, dim3(g(3)), dim3(BNT), 0, cs, b->dinst, b->items[3], b->nitems[3], 3, 0);
+        hipLaunchKernelGGL(kb_p5, dim3(g(0)), dim3(BNT), 0, cs, b->dinst, b->items[0], b->nitems[0],
+                           stage == 0 ? (int)RK2_S1 : (int)RK2_S2);
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t le = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(cs, &gr);
+    hipStreamDestroy(cs);
+    if (le != hipSuccess) {
+        if (gr) hipGraphDestroy(gr);
+        return fail(TK_EHIP, "ensemble kernel launch failed: %s", hipGetErrorString(le));
+    }
+    if (e != hipSuccess) return fail(TK_EHIP, "ensemble graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(gr);
+        return fail(TK_EHIP, "ensemble graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    b->graph = gr;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, const double *nu, tk_dtype dt,
+                                     double cfl, unsigned flags) {
+    if (!out || !n || !nu) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (count < 1) return fail(TK_EINVAL, "count must be >= 1");
+    if (dt != TK_F32) return fail(TK_EUNSUPPORTED, "ensembles run in FP32");
+    if (cfl < 0 || !std::isfinite(cfl)) return fail(TK_EINVAL, "cfl must be finite and >= 0");
+    for (int i = 0; i < count; ++i) {
+        if (!batch_size_ok(n[i])) return fail(TK_EUNSUPPORTED, "ensemble member %d: n=%d not in {16..128}", i, n[i]);
+        if (!(nu[i] >= 0) || !std::isfinite(nu[i])) return fail(TK_EINVAL, "member %d: bad nu", i);
+    }
+    tk_nsb_s *b = new (std::nothrow) tk_nsb_s();
+    if (!b) return fail(TK_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->n.assign(n, n + count);
+    b->nu.assign(nu, nu + count);
+    b->cfl = cfl;
+    if (flags >> 16) b->grid = (int)(flags >> 16);  // persistent grid size override
+    b->grids.resize(count);
+    b->hinst.resize(count);
+    b->hstate.resize(count);
+    int maxshell = 0;
+    for (int i = 0; i < count; ++i) {
+        tk_status st = ns_grid_init(&b->grids[i], n[i], TK_F32);
+        if (st != TK_OK) {
+            nsb_free(b);
+            return st;
+        }
+        const size_t fb = (size_t)n[i] * n[i] * (n[i] / 2 + 1) * sizeof(float2);
+        void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
+        if (hipMalloc(&w6, 6 * fb) != hipSuccess || hipMalloc(&aux, 3 * fb) != hipSuccess ||
+            hipMalloc(&ust, 3 * fb) != hipSuccess) {
+            if (w6) hipFree(w6);
+            if (aux) hipFree(aux);
+            nsb_free(b);
+            return fail(TK_ENOMEM, "ensemble workspace allocation failed");
+        }
+        b->bufs.push_back(w6);
+        b->bufs.push_back(aux);
+        b->bufs.push_back(ust);
+        BInst &d = b->hinst[i];
+        d.n = n[i];
+        d.K = b->grids[i].K;
+        d.KZC = b->grids[i].KZC;
+        d.u = nullptr;
+        d.w6 = (float2 *)w6;
+        d.aux = (float2 *)aux;
+        d.ust = (float2 *)ust;
+        d.tw = (const float2 *)b->grids[i].ax.twx;
+        d.nu = nu[i];
+        maxshell = std::max(maxshell, ns_num_shells(n[i]));
+    }
+    if (hipMalloc((void **)&b->dinst, sizeof(BInst) * count) != hipSuccess ||
+        hipMalloc((void **)&b->dstate, sizeof(NsState) * count) != hipSuccess ||
+        hipMalloc((void **)&b->dscratch, sizeof(double) * (NS_DIAG_BLOCKS + 2) * (NS_DIAG_HEAD + maxshell)) !=
+            hipSuccess) {
+        nsb_free(b);
+        return fail(TK_ENOMEM, "ensemble tables allocation failed");
+    }
+    for (int i = 0; i < count; ++i) b->hinst[i].st = b->dstate + i;
+    // work lists, largest grids first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
+    for (int list = 0; list < 4; ++list) {
+        std::vector<BItem> v;
+        for (int i : order) {
+            const BInst &d = b->hinst[i];
+            long nt = list == 0 ? tiles_x(d.n, d.K, d.KZC)
+                      : list == 1 ? tiles_y(d.n, d.KZC, 6)
+                      : list == 2 ? tiles_z(d.n)
+                                  : tiles_y(d.n, d.KZC, 3);
+            for (long t = 0; t < nt; ++t) v.push_back({i, (int)t});
+        }
+        b->nitems[list] = (int)v.size();
+        if (hipMalloc((void **)&b->items[list], sizeof(BItem) * v.size()) != hipSuccess ||
+            hipMemcpy(b->items[list], v.data(), sizeof(BItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            nsb_free(b);
+            return fail(TK_ENOMEM, "work list upload failed");
+        }
+    }
+    tk_status st = nsb_capture(b);
+    if (st != TK_OK) {
+        nsb_free(b);
+        return st;
+    }
+    *out = b;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_batch_step(tk_nsb_t b, void *const *uhat, double dt, int nsteps, double *t, void *stream) {
+    if (!b || !uhat) return fail(TK_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(TK_EINVAL, "nsteps must be >= 0");
+    if (b->cfl <= 0 && !(dt > 0 && std::isfinite(dt))) return fail(TK_EINVAL, "dt must be > 0 without CFL");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < b->count; ++i) {
+        if (!uhat[i]) return fail(TK_EINVAL, "uhat[%d] is NULL", i);
+        b->hinst[i].u = (float2 *)uhat[i];
+        NsState &h = b->hstate[i];
+        h = NsState{};
+        h.t = t ? t[i] : 0.0;
+        h.hfix = dt > 0 ? dt : 0.0;
+        h.h = h.hfix;
+        h.cfl_dx = b->cfl > 0 ? b->cfl * 2.0 * M_PI / b->n[i] : 0.0;
+    }
+    TK_HIP_CHECK(hipMemcpyAsync(b->dinst, b->hinst.data(), sizeof(BInst) * b->count, hipMemcpyHostToDevice, s));
+    TK_HIP_CHECK(hipMemcpyAsync(b->dstate, b->hstate.data(), sizeof(NsState) * b->count, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < nsteps; ++k) TK_HIP_CHECK(hipGraphLaunch(b->gexec, s));
+    TK_HIP_CHECK(hipMemcpyAsync(b->hstate.data(), b->dstate, sizeof(NsState) * b->count, hipMemcpyDeviceToHost, s));
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    if (t)
+        for (int i = 0; i < b->count; ++i) t[i] = b->hstate[i].t;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_batch_init_random(tk_nsb_t b, int i, const void *noise, void *u, double energy,
+                                          void *stream) {
+    if (!b || !noise || !u) return fail(TK_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->count) return fail(TK_EINVAL, "member index %d out of range", i);
+    if (!(energy > 0) || !std::isfinite(energy)) return fail(TK_EINVAL, "energy must be > 0");
+    return ns_init_random_grid(b->grids[i], noise, u, energy, b->dscratch, (hipStream_t)stream);
+}
+
+extern "C" tk_status ns_batch_diagnostics(tk_nsb_t b, int i, const void *u, double *energy, double *dissipation,
+                                          double *max_div, void *stream) {
+    if (!b || !u) return fail(TK_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->count) return fail(TK_EINVAL, "member index %d out of range", i);
+    const int nsh = ns_num_shells(b->n[i]);
+    std::vector<double> h(NS_DIAG_HEAD + nsh);
+    TK_TRY(ns_diag_run(u, b->n[i], TK_F32, nsh, b->dscratch, h.data(), (hipStream_t)stream));
+    if (energy) *energy = h[0];
+    if (dissipation) *dissipation = 2.0 * b->nu[i] * h[1];
+    if (max_div) *max_div = h[3] > 0 ? std::sqrt(h[2] / h[3]) : 0.0;
+    if (!std::isfinite(h[0])) return fail(TK_ESTATE, "member %d: energy is not finite", i);
+    return TK_OK;
+}
+
+extern "C" tk_status ns_batch_last_dt(tk_nsb_t b, double *dt) {
+    if (!b || !dt) return fail(TK_EINVAL, "NULL argument");
+    for (int i = 0; i < b->count; ++i) dt[i] = b->hstate[i].h;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_batch_destroy(tk_nsb_t b) {
+    if (b) nsb_free(b);
+    return TK_OK;
+}

@@ -63,20 +63,19 @@ template <int L, int E, int W> constexpr int strided_es() { return W + 1; }
 
 __device__ __forceinline__ bool row_kept(int r, int L, int k) { return k < 0 || r <= k || r >= L - k; }
 
+// One column tile: W columns x L points.  lds: L (W + 1) complex for the exchanges;
+// tw: the W_L^j table already in LDS.  Contains barriers: every thread calls it.
 template <typename T, int L, int E, int W>
-__global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
-                                                         long SO, long SI, const V2<T> *__restrict__ twg,
-                                                         int inv, T scale, int kl, int ks) {
+__device__ __forceinline__ void strided_tile(const V2<T> *src, V2<T> *dst, long ncols, long CB, long SO, long SI,
+                                             int inv, T scale, int kl, int ks, long tile, V2<T> *lds,
+                                             const V2<T> *tw) {
     using C = V2<T>;
     constexpr int TPL = L / E;
-    constexpr int NT = W * TPL;
     constexpr int ES = strided_es<L, E, W>();
-    __shared__ C lds[L * ES];
-    __shared__ C tw[L];
     const int tid = threadIdx.x;
     const int col = tid % W;
     const int jt = tid / W;
-    const long c = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
+    const long c = tile * W + col;
     const bool valid = c < ncols;
     const long base = valid ? (c / CB) * SO + (c % CB) : 0;
     C v[E];
@@ -87,8 +86,6 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> 
         if (inv) x.y = -x.y;
         v[i] = x;
     }
-    load_twiddles<T>(tw, twg, L, tid, NT);
-    __syncthreads();
     line_fft<T, L, E, ES>(v, lds + col, jt, tw);
     if (valid) {
 #pragma unroll
@@ -101,6 +98,22 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> 
             if (row_kept(r, L, ks)) dst[base + (long)r * SI] = x;
         }
     }
+}
+
+template <typename T, int L, int E, int W> constexpr int strided_lds_elems() { return L * strided_es<L, E, W>(); }
+
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
+                                                         long SO, long SI, const V2<T> *__restrict__ twg,
+                                                         int inv, T scale, int kl, int ks) {
+    using C = V2<T>;
+    constexpr int NT = W * (L / E);
+    __shared__ C lds[strided_lds_elems<T, L, E, W>()];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, NT);
+    __syncthreads();
+    strided_tile<T, L, E, W>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks, xcd_tile(blockIdx.x, gridDim.x), lds,
+                             tw);
 }
 
 template <typename T, int L, int E, int W>

@@ -68,6 +68,37 @@ tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &
     return launch_check("ns P5");
 }
 
+// Random solenoidal initial state: r2c of the noise, projection, 2/3 mask and k = 0
+// removed, each shell s >= 1 rescaled to s^4 exp(-2 (s/4)^2), total energy `energy`.
+tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, double energy, double *dscratch,
+                              hipStream_t s) {
+    const int n = g.n;
+    const int nshell = ns_num_shells(n);
+    TK_TRY(fft_z_r2c(g.ax, noise, u, 3, 1.0, s));
+    TK_TRY(fft_y_pass(g.ax, u, u, 3, 0, s));
+    TK_TRY(fft_x_pass(g.ax, u, u, 3, 0, 1.0 / ((double)n * n * n), s));
+    TK_TRY(ns_init_project(u, n, g.dt, s));
+    std::vector<double> h(NS_DIAG_HEAD + nshell);
+    TK_TRY(ns_diag_run(u, n, g.dt, nshell, dscratch, h.data(), s));
+    std::vector<double> fac(nshell, 0.0);
+    double total = 0;
+    for (int sh = 1; sh < nshell; ++sh) {
+        const double es = h[NS_DIAG_HEAD + sh];
+        if (es > 0) {
+            const double et = std::pow((double)sh, 4) * std::exp(-2.0 * (sh / 4.0) * (sh / 4.0));
+            fac[sh] = std::sqrt(et / es);
+            total += et;
+        }
+    }
+    if (!(total > 0)) return fail(TK_ESTATE, "noise field has no energy in the kept shells");
+    const double g2 = std::sqrt(energy / total);
+    for (auto &f : fac) f *= g2;
+    TK_HIP_CHECK(hipMemcpyAsync(dscratch, fac.data(), sizeof(double) * nshell, hipMemcpyHostToDevice, s));
+    TK_TRY(ns_scale_shells(u, n, g.dt, dscratch, nshell, s));
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
 }  // namespace tk
 
 using namespace tk;
@@ -245,32 +276,7 @@ extern "C" tk_status ns_diagnostics(tk_ns_t p, const void *u, double *energy, do
 extern "C" tk_status ns_init_random(tk_ns_t p, const void *noise, void *u, double energy, void *stream) {
     if (!p || !noise || !u) return fail(TK_EINVAL, "NULL argument");
     if (!(energy > 0) || !std::isfinite(energy)) return fail(TK_EINVAL, "energy must be > 0");
-    hipStream_t s = (hipStream_t)stream;
-    const NsGrid &g = p->g;
-    const int n = g.n;
-    TK_TRY(fft_z_r2c(g.ax, noise, u, 3, 1.0, s));
-    TK_TRY(fft_y_pass(g.ax, u, u, 3, 0, s));
-    TK_TRY(fft_x_pass(g.ax, u, u, 3, 0, 1.0 / ((double)n * n * n), s));
-    TK_TRY(ns_init_project(u, n, g.dt, s));
-    std::vector<double> h(NS_DIAG_HEAD + p->nshell);
-    TK_TRY(ns_diag_run(u, n, g.dt, p->nshell, p->dscratch, h.data(), s));
-    std::vector<double> fac(p->nshell, 0.0);
-    double total = 0;
-    for (int sh = 1; sh < p->nshell; ++sh) {
-        const double es = h[NS_DIAG_HEAD + sh];
-        if (es > 0) {
-            const double et = std::pow((double)sh, 4) * std::exp(-2.0 * (sh / 4.0) * (sh / 4.0));
-            fac[sh] = std::sqrt(et / es);
-            total += et;
-        }
-    }
-    if (!(total > 0)) return fail(TK_ESTATE, "noise field has no energy in the kept shells");
-    const double g2 = std::sqrt(energy / total);
-    for (auto &f : fac) f *= g2;
-    TK_HIP_CHECK(hipMemcpyAsync(p->dscratch, fac.data(), sizeof(double) * p->nshell, hipMemcpyHostToDevice, s));
-    TK_TRY(ns_scale_shells(u, n, g.dt, p->dscratch, p->nshell, s));
-    TK_HIP_CHECK(hipStreamSynchronize(s));
-    return TK_OK;
+    return ns_init_random_grid(p->g, noise, u, energy, p->dscratch, (hipStream_t)stream);
 }
 
 extern "C" tk_status ns_destroy(tk_ns_t p) {

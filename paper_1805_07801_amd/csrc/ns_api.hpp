@@ -32,4 +32,8 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, unsigned *umax,
                       NsState *st_set, hipStream_t s);
 
+// Random solenoidal initial state from real noise [3][n][n][n] (see ns_init_random).
+tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, double energy, double *dscratch,
+                              hipStream_t s);
+
 }  // namespace tk

@@ -59,23 +59,20 @@ __device__ __forceinline__ long kept_col(long cc, int N, int K, int KZC, int NZH
 
 // ---- P1: X-inverse with curl on load -------------------------------------------------------------
 template <typename T, int L, int E, int W>
-__global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
-                                                       int KZC, const V2<T> *__restrict__ twg) {
+__device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int KZC,
+                                           long tile, V2<T> *lds, const V2<T> *tw) {
     using C = V2<T>;
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
     constexpr int TPL = L / E;
-    constexpr int NT = W * TPL;
     constexpr int ES = W + 1;
     constexpr long FS = (long)N * N * NZH;  // field stride
     constexpr long RS = (long)N * NZH;      // x-row stride
-    __shared__ C lds[L * ES];
-    __shared__ C tw[L];
     const int tid = threadIdx.x;
     const int col = tid % W;
     const int jt = tid / W;
     const long ncols = (long)(2 * K + 1) * KZC;
-    const long cc = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
+    const long cc = tile * W + col;
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
@@ -90,8 +87,6 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ 
         a1[i] = ld ? u[FS + o] : mk<T>(0, 0);
         a2[i] = ld ? u[2 * FS + o] : mk<T>(0, 0);
     }
-    load_twiddles<T>(tw, twg, L, tid, NT);
-    __syncthreads();
 #pragma unroll 1
     for (int f = 0; f < 6; ++f) {
         C v[E];
@@ -121,30 +116,36 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ 
     }
 }
 
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
+                                                       int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    __shared__ C lds[L * (W + 1)];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
+    __syncthreads();
+    ns_p1_tile<T, L, E, W>(u, w6, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw);
+}
+
 // ---- P3: fused Z pass ------------------------------------------------------------------------------
 // Lines l = x * N + y of the 6 fields in w6 (kz < KZC nonzero); outputs c = u x omega
 // transformed back, kz < KZC, into fields 0..2 of w6 (in place: each workgroup reads all
-// six fields of its lines before it writes).
+// six fields of its lines before it writes).  lds: LPW lines of lds_line_len<L>().
 template <typename T, int L, int E, int LPW>
-__global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, int KZC,
-                                                         const V2<T> *__restrict__ twg, unsigned *umax) {
+__device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long tile, V2<T> *lds, const V2<T> *tw,
+                                           unsigned *umax) {
     using C = V2<T>;
     constexpr int N = 2 * L;
     constexpr int NZH = L + 1;
     constexpr int TPL = L / E;
-    constexpr int NT = LPW * TPL;
     constexpr int LL = lds_line_len<L>();
     constexpr long FS = (long)N * N * NZH;
-    __shared__ C lds[LPW * LL];
-    __shared__ C tw[2 * L];
     const int tid = threadIdx.x;
     const int ln = tid / TPL;
     const int jt = tid % TPL;
-    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const long l = tile * LPW + ln;
     const bool valid = l < nlines;
     C *d = lds + ln * LL;
-    load_twiddles<T>(tw, twg, 2 * L, tid, NT);
-    __syncthreads();
     // real-space samples: r[f][i] = (x[2n], x[2n+1]) at n = jt + i TPL
     C r[6][E];
 #pragma unroll
@@ -213,6 +214,17 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, 
     }
 }
 
+template <typename T, int L, int E, int LPW>
+__global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, int KZC,
+                                                         const V2<T> *__restrict__ twg, unsigned *umax) {
+    using C = V2<T>;
+    __shared__ C lds[LPW * lds_line_len<L>()];
+    __shared__ C tw[2 * L];
+    load_twiddles<T>(tw, twg, 2 * L, threadIdx.x, LPW * (L / E));
+    __syncthreads();
+    ns_p3_tile<T, L, E, LPW>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, umax);
+}
+
 // ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
 struct P5Args {
     const void *c3;    // 3 fields after P4
@@ -227,36 +239,31 @@ struct P5Args {
 };
 
 template <typename T, int L, int E, int W>
-__global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3,
-                                                       V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
-                                                       const NsState *__restrict__ st, double nu, int mode, int K,
-                                                       int KZC, const V2<T> *__restrict__ twg) {
+__device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3, V2<T> *u,
+                                           V2<T> *aux, V2<T> *ust, V2<T> *out, const NsState *__restrict__ st,
+                                           double nu, int mode, int K, int KZC, long tile, V2<T> *lds,
+                                           const V2<T> *tw) {
     using C = V2<T>;
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
     constexpr int TPL = L / E;
-    constexpr int NT = W * TPL;
     constexpr int ES = W + 1;
     constexpr long FS = (long)N * N * NZH;
     constexpr long RS = (long)N * NZH;
-    __shared__ C lds[L * ES];
-    __shared__ C tw[L];
     const int tid = threadIdx.x;
     const int col = tid % W;
     const int jt = tid / W;
     const long ncols = (long)(2 * K + 1) * KZC;
-    const long cc = (long)xcd_tile(blockIdx.x, gridDim.x) * W + col;
+    const long cc = tile * W + col;
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    load_twiddles<T>(tw, twg, L, tid, NT);
     C cf[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
 #pragma unroll
         for (int i = 0; i < E; ++i) cf[f][i] = valid ? c3[f * FS + (long)(jt + i * TPL) * RS + j] : mk<T>(0, 0);
     }
-    __syncthreads();
 #pragma unroll 1
     for (int f = 0; f < 3; ++f) {
         C v[E];
@@ -266,72 +273,87 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ 
 #pragma unroll
         for (int i = 0; i < E; ++i) cf[f][i] = v[i];
     }
-    if (!valid) return;
-    const T scale = (T)(1.0 / ((double)N * N * N));
-    const double h = st->h;
+    if (valid) {
+        const T scale = (T)(1.0 / ((double)N * N * N));
+        const double h = st->h;
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int r = jt + i * TPL;
-        if (!row_kept(r, L, K)) continue;
-        const int kx = wave_k(r, N);
-        const long o = (long)r * RS + j;
-        C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cscale(cf[2][i], scale);
-        if (add3) {
-            n0 = cadd(n0, add3[o]);
-            n1 = cadd(n1, add3[FS + o]);
-            n2 = cadd(n2, add3[2 * FS + o]);
-        }
-        const T k2 = (T)(kx * kx + ky * ky + kz * kz);
-        if (k2 > 0) {
-            const T ik2 = (T)1 / k2;
-            const C kd = cadd(cadd(cscale(n0, (T)kx), cscale(n1, (T)ky)), cscale(n2, (T)kz));
-            n0 = csub(n0, cscale(kd, (T)kx * ik2));
-            n1 = csub(n1, cscale(kd, (T)ky * ik2));
-            n2 = csub(n2, cscale(kd, (T)kz * ik2));
-        } else {
-            n0 = n1 = n2 = mk<T>(0, 0);
-        }
-        const C nn[3] = {n0, n1, n2};
-        if (mode == NS_RHS) {
+        for (int i = 0; i < E; ++i) {
+            const int r = jt + i * TPL;
+            if (!row_kept(r, L, K)) continue;
+            const int kx = wave_k(r, N);
+            const long o = (long)r * RS + j;
+            C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cscale(cf[2][i], scale);
+            if (add3) {
+                n0 = cadd(n0, add3[o]);
+                n1 = cadd(n1, add3[FS + o]);
+                n2 = cadd(n2, add3[2 * FS + o]);
+            }
+            const T k2 = (T)(kx * kx + ky * ky + kz * kz);
+            if (k2 > 0) {
+                const T ik2 = (T)1 / k2;
+                const C kd = cadd(cadd(cscale(n0, (T)kx), cscale(n1, (T)ky)), cscale(n2, (T)kz));
+                n0 = csub(n0, cscale(kd, (T)kx * ik2));
+                n1 = csub(n1, cscale(kd, (T)ky * ik2));
+                n2 = csub(n2, cscale(kd, (T)kz * ik2));
+            } else {
+                n0 = n1 = n2 = mk<T>(0, 0);
+            }
+            const C nn[3] = {n0, n1, n2};
+            if (mode == NS_RHS) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f) out[f * FS + o] = nn[f];
-            continue;
-        }
-        const double a = nu * (double)k2 * h;
-        const T e1 = (T)exp(-a);
-        const T e2 = (T)exp(-0.5 * a);
-        const T th = (T)h;
+                for (int f = 0; f < 3; ++f) out[f * FS + o] = nn[f];
+                continue;
+            }
+            const double a = nu * (double)k2 * h;
+            const T e1 = (T)exp(-a);
+            const T e2 = (T)exp(-0.5 * a);
+            const T th = (T)h;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const long q = f * FS + o;
-            const C uu = u[q];
-            const C n = nn[f];
-            switch (mode) {
-            case RK2_S1:
-                aux[q] = n;
-                ust[q] = cscale(cadd(uu, cscale(n, th)), e1);
-                break;
-            case RK2_S2:
-                u[q] = cadd(cscale(uu, e1), cscale(cadd(cscale(aux[q], e1), n), (T)0.5 * th));
-                break;
-            case RK4_S1:
-                aux[q] = cscale(n, e1);
-                ust[q] = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
-                break;
-            case RK4_S2:
-                aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
-                ust[q] = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
-                break;
-            case RK4_S3:
-                aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
-                ust[q] = cadd(cscale(uu, e1), cscale(n, th * e2));
-                break;
-            default:  // RK4_S4
-                u[q] = cadd(cscale(uu, e1), cscale(cadd(aux[q], n), th / (T)6));
-                break;
+            for (int f = 0; f < 3; ++f) {
+                const long q = f * FS + o;
+                const C uu = u[q];
+                const C n = nn[f];
+                switch (mode) {
+                case RK2_S1:
+                    aux[q] = n;
+                    ust[q] = cscale(cadd(uu, cscale(n, th)), e1);
+                    break;
+                case RK2_S2:
+                    u[q] = cadd(cscale(uu, e1), cscale(cadd(cscale(aux[q], e1), n), (T)0.5 * th));
+                    break;
+                case RK4_S1:
+                    aux[q] = cscale(n, e1);
+                    ust[q] = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
+                    break;
+                case RK4_S2:
+                    aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
+                    ust[q] = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
+                    break;
+                case RK4_S3:
+                    aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
+                    ust[q] = cadd(cscale(uu, e1), cscale(n, th * e2));
+                    break;
+                default:  // RK4_S4
+                    u[q] = cadd(cscale(uu, e1), cscale(cadd(aux[q], n), th / (T)6));
+                    break;
+                }
             }
         }
     }
+}
+
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3,
+                                                       V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
+                                                       const NsState *__restrict__ st, double nu, int mode, int K,
+                                                       int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    __shared__ C lds[L * (W + 1)];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
+    __syncthreads();
+    ns_p5_tile<T, L, E, W>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds,
+                           tw);
 }
 
 // ---- small kernels --------------------------------------------------------------------------------
