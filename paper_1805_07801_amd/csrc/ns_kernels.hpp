@@ -381,12 +381,15 @@ template <typename C> __global__ void k_zero(C *p, long n) {
 }
 
 // ---- instantiation helpers --------------------------------------------------------------------------
-// Tile shapes: P1/P5 use E = default_E(N) and W = 16 columns (8 for FP64 or when the
-// per-thread register arrays would be too large), P3 uses E = default_E(N/2), 256 threads.
+// Tile shapes.  P1/P5 hold three fields per thread, so their workgroups stay at <= 512
+// threads (the compiler caps 1024-thread workgroups at 64 VGPRs and spills): E points per
+// thread (doubled for FP32 lines >= 256) and W columns (16 for FP32, 8 for FP64, fewer if
+// that would exceed 512 threads).  P3 uses E = default_E(N/2) and 256 threads.
+template <typename T> constexpr int ns_x_E(int N) { return (sizeof(T) == 4 && N >= 256) ? 2 * default_E(N) : default_E(N); }
 template <typename T> constexpr int ns_x_W(int N) {
-    int E = default_E(N);
+    int E = ns_x_E<T>(N);
     int W = sizeof(T) == 8 ? 8 : 16;
-    while (W > 1 && W * (N / E) > 1024) W /= 2;
+    while (W > 1 && W * (N / E) > 512) W /= 2;
     while (W * (N / E) < 64) W *= 2;
     return W;
 }
@@ -405,7 +408,7 @@ struct NsKernels {
 const std::vector<NsKernels> &ns_kernels();
 
 template <typename T, int N> NsKernels make_ns_kernels() {
-    constexpr int E = default_E(N);
+    constexpr int E = ns_x_E<T>(N);
     constexpr int W = ns_x_W<T>(N);
     constexpr int L2 = N / 2;
     constexpr int E2 = default_E(L2);

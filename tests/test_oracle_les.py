@@ -1,0 +1,145 @@
+"""Pins for the oracle's closure network and LES operators (CPU only)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import diag, fft, init, les, mlp, ns
+
+
+def rand_theta(seed=0, scale=1.0):
+    Ws, bs = synth.mlp_init(seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    bs = [rng.standard_normal(b.shape) * 0.1 for b in bs]
+    return mlp.bf16_round(mlp.pack([W * scale for W in Ws], bs))
+
+
+def test_param_count_and_layout():
+    assert mlp.n_params() == 5190
+    th = np.arange(5190, dtype=float)
+    Ws, bs = mlp.unpack(th)
+    assert Ws[0].shape == (64, 9) and Ws[1].shape == (64, 64) and Ws[2].shape == (6, 64)
+    assert np.array_equal(mlp.pack(Ws, bs), th)
+    assert Ws[0][1, 0] == 9 and bs[0][0] == 576 and Ws[1][0, 0] == 640 and bs[2][5] == 5189
+
+
+def test_gelu_closed_form():
+    # GELU(0) = 0, GELU(x) -> x for large x, GELU(-x) = GELU(x) - x; Phi(1) = 0.841344746...
+    assert mlp.gelu(0.0) == 0.0
+    assert abs(mlp.gelu(1.0) - 0.8413447460685429) <= 1e-15
+    x = np.linspace(-4, 4, 17)
+    assert np.max(np.abs(mlp.gelu(-x) - (mlp.gelu(x) - x))) <= 1e-15
+    h = 1e-6
+    fd = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(fd - mlp.gelu_grad(x))) <= 1e-9
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 3.0e-3])
+    r = mlp.bf16_round(vals)
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1); 1 + 3 2^-8 -> 1 + 2^-6 (even)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7 and r[3] == 1.0 + 2 ** -6
+    assert r[4] == -2.5
+    assert abs(r[5] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+    assert np.all(mlp.bf16_bits(vals).view(np.uint16) == mlp.bf16_bits(r))
+
+
+def test_backward_matches_finite_differences():
+    th = rand_theta(3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((9, 40))
+    dy = rng.standard_normal((6, 40))
+    g = mlp.backward(th, x, dy)
+
+    def L(t):
+        return float(np.sum(dy * mlp.forward(t, x)))
+
+    idx = rng.choice(5190, 60, replace=False)
+    idx = np.concatenate([idx, [0, 575, 576, 639, 640, 4735, 4736, 4799, 4800, 5183, 5184, 5189]])
+    h = 1e-5
+    for i in idx:
+        e = np.zeros(5190)
+        e[i] = h
+        fd = (L(th + e) - L(th - e)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_mse_and_adam_first_step():
+    y = np.array([[1.0, 2.0], [3.0, 5.0]])
+    t = np.array([[0.0, 2.0], [3.0, 4.0]])
+    Lv, dy = mlp.mse_loss(y, t)
+    assert Lv == 0.5 and np.array_equal(dy, np.array([[0.5, 0.0], [0.0, 0.5]]))
+    # the first Adam step moves each weight by lr * g / (|g| + eps)
+    th = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 0.0])
+    th1, m, v = mlp.adam(th, np.zeros(3), np.zeros(3), g, 1, 1e-2)
+    assert np.allclose(th1, th - 1e-2 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def band_limited_state(n, kmax, seed):
+    uh = init.random_solenoidal(synth.gaussian_field((3, n, n, n), seed))
+    kx, ky, kz = fft.wavenumbers(n)
+    keep = (np.abs(kx) <= kmax) & (np.abs(ky) <= kmax) & (kz <= kmax)
+    return uh * keep
+
+
+def test_filter_truncation_and_band_limited_stress_vanishes():
+    """A DNS field with |k_i| <= 10 passes the kc = 21 box unchanged, and since every
+    product then lives in |k_i| <= 20 < 32 the sub-grid stress is exactly zero."""
+    n_dns, n_les, kc = 96, 64, 21
+    uh = band_limited_state(n_dns, 10, seed=2)
+    ub = les.filtered_velocity(uh, n_les, kc)
+    assert abs(diag.energy(ub) - diag.energy(uh)) <= 1e-14
+    assert np.max(np.abs(les.sgs_stress(uh, n_les, kc))) <= 1e-13
+    # truncation round trip (coarse -> fine -> coarse) is the identity on kept modes
+    back = les.truncate(les.truncate(ub, n_dns, kc), n_les, kc)
+    assert np.max(np.abs(back - ub)) == 0
+
+
+def test_stress_of_single_high_mode():
+    """u = (cos 25 z, 0, 0) has no resolved part for kc = 21, and u_x^2 = (1 + cos 50 z)/2,
+    so tau_xx = 1/2 and every other component is 0."""
+    n_dns, n_les, kc = 96, 64, 21
+    z = synth.grid(n_dns)
+    u = np.zeros((3, n_dns, n_dns, n_dns))
+    u[0] = np.cos(25 * z)[None, None, :]
+    tau = les.sgs_stress(fft.rfft3(u), n_les, kc)
+    assert np.max(np.abs(tau[0] - 0.5)) <= 1e-13
+    assert np.max(np.abs(tau[1:])) <= 1e-13
+
+
+def test_gradient_features_taylor_green():
+    n = 32
+    uh = fft.rfft3(synth.taylor_green(n))
+    g = les.gradients(uh)
+    x = synth.grid(n)
+    X, Y, Z = x[:, None, None], x[None, :, None], x[None, None, :]
+    # d_x u_x = cos x cos y cos z ; d_y u_x = -sin x sin y cos z ; d_z u_y = cos x sin y sin z
+    assert np.max(np.abs(g[0] - np.cos(X) * np.cos(Y) * np.cos(Z))) <= 1e-14
+    assert np.max(np.abs(g[1] + np.sin(X) * np.sin(Y) * np.cos(Z))) <= 1e-14
+    assert np.max(np.abs(g[5] - np.cos(X) * np.sin(Y) * np.sin(Z))) <= 1e-14
+    assert np.max(np.abs(g[6:])) <= 1e-14
+    # trace = divergence = 0
+    assert np.max(np.abs(g[0] + g[4] + g[8])) <= 1e-14
+
+
+def test_sgs_divergence_of_uniform_and_linear_stress():
+    """A constant stress has no divergence; tau_xz = sin z gives -d_z tau_xz = -cos z on x."""
+    n = 16
+    z = synth.grid(n)
+    tau = np.zeros((6, n, n, n))
+    tau[0] = 3.0
+    assert np.max(np.abs(les.sgs_divergence(tau))) <= 1e-15
+    tau[4] = np.sin(z)[None, None, :]
+    d = fft.irfft3(les.sgs_divergence(tau))
+    assert np.max(np.abs(d[0] + np.cos(z)[None, None, :])) <= 1e-14
+    assert np.max(np.abs(d[2])) <= 1e-14  # d_x tau_xz = 0
+
+
+def test_les_rhs_without_model_is_plain_rhs():
+    n = 16
+    uh = init.random_solenoidal(synth.gaussian_field((3, n, n, n), 8))
+    assert np.max(np.abs(les.les_rhs(uh, None, 1.0, 1.0) - ns.rhs(uh))) == 0
+    th = rand_theta(1, scale=0.0)  # zero weights, zero-ish biases -> constant stress -> no divergence
+    th[:] = 0
+    assert np.max(np.abs(les.les_rhs(uh, th, 1.0, 1.0) - ns.rhs(uh))) <= 1e-18
