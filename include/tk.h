@@ -209,6 +209,70 @@ tk_status ns_batch_last_dt(tk_nsb_t b, double *dt);
 
 tk_status ns_batch_destroy(tk_nsb_t b);
 
+/* ------------------------------------------------------------------------------------
+ * Learned sub-grid closure for coarse LES (not part of the paper's solver: a pointwise
+ * network stands in for the sub-grid stress of a filtered field).
+ * Network: 9 inputs (the filtered velocity gradients d_j ubar_i, component 3 i + j,
+ * divided by in_scale) -> 64 GELU -> 64 GELU -> 6 outputs (tau_xx, yy, zz, xy, xz, yz,
+ * in units of out_scale); GELU(x) = x/2 (1 + erf(x/sqrt 2)).  Parameters: TK_MLP_NPARAM
+ * BF16 values in the order W1[64][9], b1[64], W2[64][64], b2[64], W3[6][64], b3[6];
+ * every product and sum is FP32.  Point arrays are structure-of-arrays: x9 [9][M],
+ * y6 / t6 / dy6 [6][M], FP32, device memory.
+ * ------------------------------------------------------------------------------------ */
+#define TK_MLP_NPARAM 5190
+
+typedef struct {
+    const uint16_t *w; /* device: TK_MLP_NPARAM BF16 parameters */
+    float in_scale;    /* inputs are divided by it (> 0) */
+    float out_scale;   /* outputs are multiplied by it (> 0) */
+} tk_mlp;
+
+typedef struct {
+    float *w, *m, *v;  /* device: FP32 master parameters and Adam moments (TK_MLP_NPARAM each) */
+    float lr, beta1, beta2, eps;
+    int step;          /* updates done so far; incremented by sgs_adam_step */
+} tk_adam;
+
+/* y6 = out_scale * f(x9 / in_scale) at M points. */
+tk_status sgs_mlp_forward(const tk_mlp *w, const float *x9, float *y6, long M, void *stream);
+
+/* grad (device, TK_MLP_NPARAM FP32) = sum over the M points of (d f(x9/in_scale) / d theta)^T
+ * dy6, with dy6 the gradient with respect to the normalised network outputs.  The point
+ * sums are formed per slice and added over slices in a fixed order in FP64. */
+tk_status sgs_mlp_backward(const tk_mlp *w, const float *x9, const float *dy6, long M, float *grad,
+                           void *stream);
+
+/* Mean-square loss in normalised units, L = mean over the 6 M values of (f(x9/in_scale) -
+ * t6/out_scale)^2 (host, FP64; may be NULL: then no synchronisation), and its gradient
+ * into grad (as sgs_mlp_backward with dy6 = dL/dy). */
+tk_status sgs_mlp_loss_grad(const tk_mlp *w, const float *x9, const float *t6, long M, float *grad,
+                            double *loss, void *stream);
+
+/* One Adam update (Kingma & Ba) of opt->w from grad; increments opt->step and writes the
+ * BF16-rounded (nearest, ties to even) parameters to w_bf16. */
+tk_status sgs_adam_step(tk_adam *opt, const float *grad, uint16_t *w_bf16, void *stream);
+
+/* BF16 (nearest, ties to even) copy of n FP32 values. */
+tk_status sgs_weights_to_bf16(const float *w, uint16_t *w_bf16, int n, void *stream);
+
+/* LES steps (FP32, IF-RK2, the solver's CFL or fixed dt): the right-hand side is
+ * P M [F(u x omega) - i k_j F(tau_ij)] with tau = out_scale f(grad(u)/in_scale) evaluated
+ * from the stage state on the grid.  w_or_null = NULL: plain DNS right-hand side.  If
+ * the weights hold a non-finite value the steps run without the model (*fallback = 1);
+ * if the state is not finite after the steps, it is restored and the steps are redone
+ * without the model (*fallback = 2); else *fallback = 0 (fallback may be NULL).
+ * Synchronises. */
+tk_status les_step(tk_ns_t ns, const tk_mlp *w_or_null, void *uhat_inout, double dt, int nsteps,
+                   double *t_inout, int *fallback, void *stream);
+
+/* Training data from a DNS state uhat_dns [3][n_dns][n_dns][n_dns/2+1] (FP32, not
+ * modified): box filter |k_i| <= kc (3 kc < n_les), truncated onto the n_les grid:
+ * grad9 [9][n_les^3] = d_j ubar_i, tau6 [6][n_les^3] = G(u_i u_j) - ubar_i ubar_j with the
+ * first product formed on the DNS grid, and optionally ubar_hat [3][n_les][n_les][n_les/2+1].
+ * Allocates and frees its own workspace (about 6 DNS fields).  Synchronises. */
+tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, int kc, float *grad9, float *tau6,
+                         void *ubar_hat, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

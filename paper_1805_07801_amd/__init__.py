@@ -22,6 +22,15 @@ class TkError(RuntimeError):
         self.status = status
 
 
+class TkMlp(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("in_scale", ctypes.c_float), ("out_scale", ctypes.c_float)]
+
+
+class TkAdam(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("m", ctypes.c_void_p), ("v", ctypes.c_void_p), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("step", ctypes.c_int)]
+
+
 class NsConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("scheme", ctypes.c_int), ("flags", ctypes.c_uint)]
@@ -59,6 +68,13 @@ def _declare(L):
         "ns_batch_diagnostics": ([vp, i, vp, P(d), P(d), P(d), vp], i),
         "ns_batch_last_dt": ([vp, P(d)], i),
         "ns_batch_destroy": ([vp], i),
+        "sgs_mlp_forward": ([P(TkMlp), vp, vp, ctypes.c_long, vp], i),
+        "sgs_mlp_backward": ([P(TkMlp), vp, vp, ctypes.c_long, vp, vp], i),
+        "sgs_mlp_loss_grad": ([P(TkMlp), vp, vp, ctypes.c_long, vp, P(d), vp], i),
+        "sgs_adam_step": ([P(TkAdam), vp, vp, vp], i),
+        "sgs_weights_to_bf16": ([vp, vp, i, vp], i),
+        "les_step": ([vp, P(TkMlp), vp, d, i, P(d), P(i), vp], i),
+        "les_filter_dns": ([vp, i, i, i, vp, vp, vp, vp], i),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -380,3 +396,77 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+MLP_NPARAM = 5190
+
+
+class Closure:
+    """Pointwise sub-grid stress network (BF16 parameters on the GPU, FP32 master copy and
+    Adam moments) with its input/output scales."""
+
+    def __init__(self, theta, in_scale=1.0, out_scale=1.0, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        th = torch.as_tensor(theta, dtype=torch.float32).reshape(-1)
+        if th.numel() != MLP_NPARAM:
+            raise TkError(TK_EINVAL, "need %d parameters" % MLP_NPARAM)
+        self.w32 = th.cuda().contiguous()
+        self.m = torch.zeros_like(self.w32)
+        self.v = torch.zeros_like(self.w32)
+        self.wb = torch.empty(MLP_NPARAM, dtype=torch.int16, device="cuda")
+        check(lib().sgs_weights_to_bf16(_ptr(self.w32), _ptr(self.wb), MLP_NPARAM, _stream()))
+        self.grad = torch.zeros(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        self.in_scale = float(in_scale)
+        self.out_scale = float(out_scale)
+        self.opt = TkAdam(self.w32.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), lr, beta1, beta2, eps, 0)
+
+    def desc(self):
+        return TkMlp(self.wb.data_ptr(), self.in_scale, self.out_scale)
+
+    def bf16_bits(self):
+        return self.wb.cpu().numpy().view("uint16")
+
+    def forward(self, x9, out=None):
+        import torch
+        M = x9.shape[-1]
+        out = torch.empty((6, M), dtype=torch.float32, device="cuda") if out is None else out
+        d = self.desc()
+        check(lib().sgs_mlp_forward(ctypes.byref(d), _ptr(x9), _ptr(out), M, _stream()))
+        return out
+
+    def backward(self, x9, dy6):
+        d = self.desc()
+        check(lib().sgs_mlp_backward(ctypes.byref(d), _ptr(x9), _ptr(dy6), x9.shape[-1], _ptr(self.grad), _stream()))
+        return self.grad
+
+    def loss_grad(self, x9, t6):
+        d = self.desc()
+        loss = ctypes.c_double()
+        check(lib().sgs_mlp_loss_grad(ctypes.byref(d), _ptr(x9), _ptr(t6), x9.shape[-1], _ptr(self.grad),
+                                      ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def adam_step(self):
+        check(lib().sgs_adam_step(ctypes.byref(self.opt), _ptr(self.grad), _ptr(self.wb), _stream()))
+
+
+def les_filter_dns(uhat_dns, n_les, kc, with_ubar=False):
+    """(grad9 [9][M], tau6 [6][M], ubar_hat or None) for the box filter |k_i| <= kc."""
+    import torch
+    n = uhat_dns.shape[-3]
+    M = n_les ** 3
+    g = torch.empty((9, M), dtype=torch.float32, device="cuda")
+    t = torch.empty((6, M), dtype=torch.float32, device="cuda")
+    ub = torch.empty((3, n_les, n_les, n_les // 2 + 1), dtype=torch.complex64, device="cuda") if with_ubar else None
+    check(lib().les_filter_dns(_ptr(uhat_dns), n, n_les, kc, _ptr(g), _ptr(t), _ptr(ub), _stream()))
+    return g, t, ub
+
+
+def les_step(ns, closure, u, dt, nsteps=1, t=0.0):
+    """LES steps with the closure (None: plain right-hand side).  Returns (t, fallback)."""
+    tt = ctypes.c_double(t)
+    fb = ctypes.c_int(-1)
+    d = closure.desc() if closure is not None else None
+    check(lib().les_step(ns.h, ctypes.byref(d) if d is not None else None, _ptr(u), float(dt), int(nsteps),
+                         ctypes.byref(tt), ctypes.byref(fb), _stream()))
+    return tt.value, fb.value

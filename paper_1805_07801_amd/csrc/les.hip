@@ -1,0 +1,672 @@
+// Learned sub-grid closure for coarse LES: the pointwise network (forward, backward,
+// Adam), the filtered-DNS training data, and the LES step that adds the closure's
+// stress divergence to the pseudo-spectral right-hand side.
+//
+// Network: 9 filtered velocity gradients (divided by in_scale) -> 64 GELU -> 64 GELU ->
+// 6 stress components (times out_scale); parameters are BF16, every product and sum is
+// FP32.  Flat parameter order W1[64][9], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "ns_api.hpp"
+#include "reduce.hpp"
+
+namespace tk {
+
+constexpr int NP = 5190;
+constexpr int OW1 = 0, OB1 = 576, OW2 = 640, OB2 = 4736, OW3 = 4800, OB3 = 5184;
+
+__device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float((unsigned)b << 16); }
+__device__ __forceinline__ uint16_t f32_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ---- forward ------------------------------------------------------------------------------------------
+constexpr int MB = 256;
+
+__device__ __forceinline__ void load_weights(float *w, const uint16_t *__restrict__ wb) {
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) w[i] = bf16_f32(wb[i]);
+    __syncthreads();
+}
+
+// Point p: h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), y = W3 h2 + b3, one point per thread,
+// weights broadcast from LDS.
+__global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
+                                               float *__restrict__ y6, long M, float in_inv, float out_scale) {
+    __shared__ float w[NP];
+    load_weights(w, wb);
+    for (long p = (long)blockIdx.x * MB + threadIdx.x; p < M; p += (long)gridDim.x * MB) {
+        float x[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) x[c] = x9[c * M + p] * in_inv;
+        float h1[64];
+#pragma unroll
+        for (int o = 0; o < 64; ++o) {
+            float a = w[OB1 + o];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) a = fmaf(w[OW1 + o * 9 + c], x[c], a);
+            h1[o] = gelu(a);
+        }
+        float y[6];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) y[o] = w[OB3 + o];
+#pragma unroll 4
+        for (int o = 0; o < 64; ++o) {
+            float a = w[OB2 + o];
+#pragma unroll
+            for (int i = 0; i < 64; ++i) a = fmaf(w[OW2 + o * 64 + i], h1[i], a);
+            const float h2 = gelu(a);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) y[q] = fmaf(w[OW3 + q * 64 + o], h2, y[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) y6[q * M + p] = y[q] * out_scale;
+    }
+}
+
+// ---- loss and backward ------------------------------------------------------------------------------
+// Per point: forward, dy (given, or 2 (y - t/out_scale) / (6 M) from targets), backprop to
+// da2 = (W3^T dy) gelu'(a2) and da1 = (W2^T da2) gelu'(a1).  Writes the factors of the
+// per-parameter sums: X[9][M] (normalised input), H1[64][M], H2[64][M], DA1[64][M],
+// DA2[64][M], DY[6][M]; loss partial sums per block (FP64).
+struct BwdBufs {
+    float *X, *H1, *H2, *DA1, *DA2, *DY;
+};
+
+__global__ __launch_bounds__(MB) void k_mlp_bwd_a(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
+                                                 const float *__restrict__ t6, const float *__restrict__ dy6,
+                                                 long M, float in_inv, float out_inv, BwdBufs B,
+                                                 double *__restrict__ lpart) {
+    __shared__ float w[NP];
+    __shared__ double sh[MB / 64];
+    load_weights(w, wb);
+    const float dscale = 2.0f / (6.0f * (float)M);
+    double lacc = 0;
+    for (long p = (long)blockIdx.x * MB + threadIdx.x; p < M; p += (long)gridDim.x * MB) {
+        float x[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            x[c] = x9[c * M + p] * in_inv;
+            B.X[c * M + p] = x[c];
+        }
+        // h1 = gelu(a1) stays in registers; gelu'(a1) is parked in DA1 until dh1 is known
+        float h1[64];
+#pragma unroll
+        for (int o = 0; o < 64; ++o) {
+            float a = w[OB1 + o];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) a = fmaf(w[OW1 + o * 9 + c], x[c], a);
+            h1[o] = gelu(a);
+            B.H1[o * M + p] = h1[o];
+            B.DA1[o * M + p] = gelu_grad(a);
+        }
+        float y[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) y[q] = w[OB3 + q];
+        // a2 kept only through H2 / gelu'(a2): store gelu'(a2) in DA2 temporarily
+#pragma unroll 4
+        for (int o = 0; o < 64; ++o) {
+            float a = w[OB2 + o];
+#pragma unroll
+            for (int i = 0; i < 64; ++i) a = fmaf(w[OW2 + o * 64 + i], h1[i], a);
+            const float h2 = gelu(a);
+            B.H2[o * M + p] = h2;
+            B.DA2[o * M + p] = gelu_grad(a);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) y[q] = fmaf(w[OW3 + q * 64 + o], h2, y[q]);
+        }
+        float dy[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (t6) {
+                const float d = y[q] - t6[q * M + p] * out_inv;
+                lacc += (double)d * d;
+                dy[q] = d * dscale;
+            } else {
+                dy[q] = dy6[q * M + p];
+            }
+            B.DY[q * M + p] = dy[q];
+        }
+        // da2 = (W3^T dy) * gelu'(a2); dh1 = W2^T da2
+        float dh1[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) dh1[i] = 0.f;
+#pragma unroll 4
+        for (int o = 0; o < 64; ++o) {
+            float g = 0.f;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g = fmaf(w[OW3 + q * 64 + o], dy[q], g);
+            const float da2 = g * B.DA2[o * M + p];
+            B.DA2[o * M + p] = da2;
+#pragma unroll
+            for (int i = 0; i < 64; ++i) dh1[i] = fmaf(w[OW2 + o * 64 + i], da2, dh1[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 64; ++i) B.DA1[i * M + p] = dh1[i] * B.DA1[i * M + p];
+    }
+    if (t6) {
+        lacc = block_sum(lacc, sh);
+        if (threadIdx.x == 0) lpart[blockIdx.x] = lacc;
+    }
+}
+
+// Per-slice partial sums of every parameter's gradient:
+//   W1[o][c]: sum_p DA1[o][p] X[c][p]    b1[o]: sum_p DA1[o][p]
+//   W2[o][i]: sum_p DA2[o][p] H1[i][p]   b2[o]: sum_p DA2[o][p]
+//   W3[q][i]: sum_p DY[q][p]  H2[i][p]   b3[q]: sum_p DY[q][p]
+// A slice of points is staged through LDS in chunks of PC points; thread t owns
+// parameters t, t + 256, ... (at most 21).
+constexpr int PC = 32;
+constexpr int PPT = (NP + MB - 1) / MB;
+
+__global__ __launch_bounds__(MB) void k_mlp_bwd_b(BwdBufs B, long M, long slice, float *__restrict__ part) {
+    __shared__ float sX[9][PC], sH1[64][PC], sH2[64][PC], sD1[64][PC], sD2[64][PC], sDY[6][PC];
+    __shared__ float one[PC];
+    const long p0 = (long)blockIdx.x * slice;
+    const long p1 = p0 + slice < M ? p0 + slice : M;
+    // decode owned parameters into (A row, B row) pointers inside the LDS chunk
+    const float *Ar[PPT];
+    const float *Br[PPT];
+    float acc[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int j = threadIdx.x + q * MB;
+        acc[q] = 0.f;
+        Ar[q] = one;
+        Br[q] = one;
+        if (j >= NP) continue;
+        if (j < OB1) { Ar[q] = sD1[(j - OW1) / 9]; Br[q] = sX[(j - OW1) % 9]; }
+        else if (j < OW2) { Ar[q] = sD1[j - OB1]; Br[q] = one; }
+        else if (j < OB2) { Ar[q] = sD2[(j - OW2) / 64]; Br[q] = sH1[(j - OW2) % 64]; }
+        else if (j < OW3) { Ar[q] = sD2[j - OB2]; Br[q] = one; }
+        else if (j < OB3) { Ar[q] = sDY[(j - OW3) / 64]; Br[q] = sH2[(j - OW3) % 64]; }
+        else { Ar[q] = sDY[j - OB3]; Br[q] = one; }
+    }
+    for (long c0 = p0; c0 < p1; c0 += PC) {
+        __syncthreads();
+        const int np = (int)(p1 - c0 < PC ? p1 - c0 : PC);
+        for (int e = threadIdx.x; e < 271 * PC; e += MB) {
+            const int row = e / PC, pp = e % PC;
+            const bool ok = pp < np;
+            const long gp = c0 + pp;
+            float v = 0.f;
+            if (row < 9) { if (ok) v = B.X[row * M + gp]; sX[row][pp] = v; }
+            else if (row < 73) { if (ok) v = B.H1[(row - 9) * M + gp]; sH1[row - 9][pp] = v; }
+            else if (row < 137) { if (ok) v = B.H2[(row - 73) * M + gp]; sH2[row - 73][pp] = v; }
+            else if (row < 201) { if (ok) v = B.DA1[(row - 137) * M + gp]; sD1[row - 137][pp] = v; }
+            else if (row < 265) { if (ok) v = B.DA2[(row - 201) * M + gp]; sD2[row - 201][pp] = v; }
+            else { if (ok) v = B.DY[(row - 265) * M + gp]; sDY[row - 265][pp] = v; }
+        }
+        if (threadIdx.x < PC) one[threadIdx.x] = threadIdx.x < np ? 1.f : 0.f;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            float a = 0.f;
+#pragma unroll 8
+            for (int pp = 0; pp < PC; ++pp) a = fmaf(Ar[q][pp], Br[q][pp], a);
+            acc[q] += a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int j = threadIdx.x + q * MB;
+        if (j < NP) part[(long)blockIdx.x * NP + j] = acc[q];
+    }
+}
+
+// Fixed-order FP64 sum of the slice partials.
+__global__ void k_mlp_bwd_c(const float *__restrict__ part, int nslice, float *__restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < NP) {
+        double a = 0;
+        for (int s = 0; s < nslice; ++s) a += (double)part[(long)s * NP + j];
+        grad[j] = (float)a;
+    }
+}
+
+// ---- Adam (Kingma & Ba) ---------------------------------------------------------------------------
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, uint16_t *__restrict__ wb, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < NP) {
+        const float gj = g[j];
+        const float mj = b1 * m[j] + (1.f - b1) * gj;
+        const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+        m[j] = mj;
+        v[j] = vj;
+        const float wj = w[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+        w[j] = wj;
+        wb[j] = f32_bf16(wj);
+    }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb, int n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) wb[j] = f32_bf16(w[j]);
+}
+
+__global__ void k_count_nonfinite(const uint16_t *__restrict__ wb, int n, int *__restrict__ cnt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n && (wb[j] & 0x7f80u) == 0x7f80u) atomicAdd(cnt, 1);
+}
+
+// ---- spectral helpers ---------------------------------------------------------------------------------
+// g[3 i + j] = i k_j u^_i (Nyquist derivative taken as zero), 9 fields.
+__global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g, int N) {
+    const int NZH = N / 2 + 1;
+    const long FS = (long)N * N * NZH;
+    for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < FS; m += (long)gridDim.x * blockDim.x) {
+        const int kz0 = (int)(m % NZH);
+        const long xy = m / NZH;
+        const int y = (int)(xy % N), x = (int)(xy / N);
+        const int k[3] = {2 * x == N ? 0 : (x < N / 2 ? x : x - N), 2 * y == N ? 0 : (y < N / 2 ? y : y - N),
+                          2 * kz0 == N ? 0 : kz0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float2 a = u[i * FS + m];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) g[(3 * i + j) * FS + m] = make_float2(-a.y * k[j], a.x * k[j]);
+        }
+    }
+}
+
+// add3_i = -i sum_j k_j tau^_ij, tau components (xx, yy, zz, xy, xz, yz).
+__global__ void k_sgs_div(const float2 *__restrict__ th, float2 *__restrict__ add3, int N) {
+    const int NZH = N / 2 + 1;
+    const long FS = (long)N * N * NZH;
+    for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < FS; m += (long)gridDim.x * blockDim.x) {
+        const int kz0 = (int)(m % NZH);
+        const long xy = m / NZH;
+        const int y = (int)(xy % N), x = (int)(xy / N);
+        const float k0 = 2 * x == N ? 0 : (x < N / 2 ? x : x - N), k1 = 2 * y == N ? 0 : (y < N / 2 ? y : y - N),
+                    k2 = 2 * kz0 == N ? 0 : kz0;
+        const float2 xx = th[m], yy = th[FS + m], zz = th[2 * FS + m], xy_ = th[3 * FS + m], xz = th[4 * FS + m],
+                     yz = th[5 * FS + m];
+        const float2 s0 = make_float2(k0 * xx.x + k1 * xy_.x + k2 * xz.x, k0 * xx.y + k1 * xy_.y + k2 * xz.y);
+        const float2 s1 = make_float2(k0 * xy_.x + k1 * yy.x + k2 * yz.x, k0 * xy_.y + k1 * yy.y + k2 * yz.y);
+        const float2 s2 = make_float2(k0 * xz.x + k1 * yz.x + k2 * zz.x, k0 * xz.y + k1 * yz.y + k2 * zz.y);
+        // -i s = (s.y, -s.x)
+        add3[m] = make_float2(s0.y, -s0.x);
+        add3[FS + m] = make_float2(s1.y, -s1.x);
+        add3[2 * FS + m] = make_float2(s2.y, -s2.x);
+    }
+}
+
+// Box filter by truncation: modes |kx|, |ky|, kz <= kc of an n1 half spectrum onto an n2
+// half spectrum (zero elsewhere), nf fields.
+__global__ void k_truncate(const float2 *__restrict__ src, int n1, float2 *__restrict__ dst, int n2, int kc,
+                           int nf) {
+    const int h1 = n1 / 2 + 1, h2 = n2 / 2 + 1;
+    const long F2 = (long)n2 * n2 * h2, F1 = (long)n1 * n1 * h1;
+    for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < F2 * nf; m += (long)gridDim.x * blockDim.x) {
+        const int f = (int)(m / F2);
+        const long r = m % F2;
+        const int kz = (int)(r % h2);
+        const long xy = r / h2;
+        const int y = (int)(xy % n2), x = (int)(xy / n2);
+        const int kx = x < n2 / 2 ? x : x - n2, ky = y < n2 / 2 ? y : y - n2;
+        float2 v = make_float2(0.f, 0.f);
+        if (abs(kx) <= kc && abs(ky) <= kc && kz <= kc) {
+            const int sx = kx < 0 ? kx + n1 : kx, sy = ky < 0 ? ky + n1 : ky;
+            v = src[f * F1 + ((long)sx * n1 + sy) * h1 + kz];
+        }
+        dst[m] = v;
+    }
+}
+
+__global__ void k_mul(const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ o, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        o[i] = a[i] * b[i];
+}
+
+// tau_q = G(u_i u_j) - ubar_i ubar_j, q over the 6 pairs.
+__global__ void k_tau(const float *__restrict__ guu, const float *__restrict__ ub, float *__restrict__ tau, long M) {
+    const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) tau[q * M + p] = guu[q * M + p] - ub[pi[q] * M + p] * ub[pj[q] * M + p];
+    }
+}
+
+static unsigned ew_blocks(long n) { return (unsigned)std::min<long>(16384, std::max<long>(1, (n + 255) / 256)); }
+
+// ---- backward scratch (grow-only, per process) ---------------------------------------------------------
+struct BwdScratch {
+    std::mutex mu;
+    long M = 0;
+    float *buf = nullptr;
+    float *part = nullptr;
+    double *lpart = nullptr;
+    int dev = -1;
+};
+static BwdScratch g_bwd;
+
+static tk_status bwd_scratch(long M, BwdBufs *B, float **part, double **lpart, int nslice, int nblk) {
+    int dev = 0;
+    TK_HIP_CHECK(hipGetDevice(&dev));
+    if (M > g_bwd.M || dev != g_bwd.dev) {
+        if (g_bwd.buf) hipFree(g_bwd.buf);
+        if (g_bwd.part) hipFree(g_bwd.part);
+        if (g_bwd.lpart) hipFree(g_bwd.lpart);
+        g_bwd.buf = nullptr;
+        g_bwd.part = nullptr;
+        g_bwd.lpart = nullptr;
+        g_bwd.M = 0;
+        if (hipMalloc((void **)&g_bwd.buf, sizeof(float) * 271 * (size_t)M) != hipSuccess ||
+            hipMalloc((void **)&g_bwd.part, sizeof(float) * (size_t)NP * 1024) != hipSuccess ||
+            hipMalloc((void **)&g_bwd.lpart, sizeof(double) * 4096) != hipSuccess)
+            return fail(TK_ENOMEM, "network backward scratch allocation failed");
+        g_bwd.M = M;
+        g_bwd.dev = dev;
+    }
+    float *b = g_bwd.buf;
+    B->X = b;
+    B->H1 = b + 9 * M;
+    B->H2 = b + 73 * M;
+    B->DA1 = b + 137 * M;
+    B->DA2 = b + 201 * M;
+    B->DY = b + 265 * M;
+    *part = g_bwd.part;
+    *lpart = g_bwd.lpart;
+    (void)nslice;
+    (void)nblk;
+    return TK_OK;
+}
+
+static tk_status mlp_check(const tk_mlp *w) {
+    if (!w || !w->w) return fail(TK_EINVAL, "network weights are NULL");
+    if (!(w->in_scale > 0) || !(w->out_scale > 0) || !std::isfinite(w->in_scale) || !std::isfinite(w->out_scale))
+        return fail(TK_EINVAL, "network scales must be finite and > 0");
+    return TK_OK;
+}
+
+tk_status mlp_forward_run(const tk_mlp *w, const float *x9, float *y6, long M, hipStream_t s) {
+    const unsigned nb = (unsigned)std::min<long>(4096, std::max<long>(1, (M + MB - 1) / MB));
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(MB), 0, s, w->w, x9, y6, M, 1.0f / w->in_scale, w->out_scale);
+    return launch_check("network forward");
+}
+
+static tk_status mlp_backward_run(const tk_mlp *w, const float *x9, const float *t6, const float *dy6, long M,
+                                  float *grad, double *loss, hipStream_t s) {
+    BwdBufs B;
+    float *part;
+    double *lpart;
+    const int nblk_a = (int)std::min<long>(4096, std::max<long>(1, (M + MB - 1) / MB));
+    const int nslice = (int)std::min<long>(1024, std::max<long>(1, (M + 255) / 256));
+    const long slice = (M + nslice - 1) / nslice;
+    TK_TRY(bwd_scratch(M, &B, &part, &lpart, nslice, nblk_a));
+    hipLaunchKernelGGL(k_mlp_bwd_a, dim3(nblk_a), dim3(MB), 0, s, w->w, x9, t6, dy6, M, 1.0f / w->in_scale,
+                       1.0f / w->out_scale, B, lpart);
+    TK_TRY(launch_check("network backward (points)"));
+    hipLaunchKernelGGL(k_mlp_bwd_b, dim3(nslice), dim3(MB), 0, s, B, M, slice, part);
+    TK_TRY(launch_check("network backward (slices)"));
+    hipLaunchKernelGGL(k_mlp_bwd_c, dim3(cdiv(NP, 256)), dim3(256), 0, s, part, nslice, grad);
+    TK_TRY(launch_check("network backward (sum)"));
+    if (loss) {
+        std::vector<double> h(nblk_a);
+        TK_HIP_CHECK(hipMemcpyAsync(h.data(), lpart, sizeof(double) * nblk_a, hipMemcpyDeviceToHost, s));
+        TK_HIP_CHECK(hipStreamSynchronize(s));
+        double a = 0;
+        for (double v : h) a += v;
+        *loss = a / (6.0 * (double)M);
+    }
+    return TK_OK;
+}
+
+// ---- LES workspace and one closure evaluation --------------------------------------------------------
+void les_work_free(LesWork &w) {
+    void *ps[] = {w.gsp, w.greal, w.tau, w.tauh, w.add3, w.backup};
+    for (void *p : ps)
+        if (p) hipFree(p);
+    w = LesWork{};
+}
+
+static tk_status les_work_alloc(tk_ns_t p) {
+    LesWork &w = p->les;
+    if (w.gsp) return TK_OK;
+    const int n = p->g.n;
+    const size_t fb = p->fbytes;
+    const size_t rb = sizeof(float) * (size_t)n * n * n;
+    if (hipMalloc(&w.gsp, 9 * fb) != hipSuccess || hipMalloc((void **)&w.greal, 9 * rb) != hipSuccess ||
+        hipMalloc((void **)&w.tau, 6 * rb) != hipSuccess || hipMalloc(&w.tauh, 6 * fb) != hipSuccess ||
+        hipMalloc(&w.add3, 3 * fb) != hipSuccess || hipMalloc(&w.backup, 3 * fb) != hipSuccess) {
+        les_work_free(w);
+        return fail(TK_ENOMEM, "LES workspace allocation failed");
+    }
+    return TK_OK;
+}
+
+// add3 = -i k_j tau^_ij with tau = out_scale f(grad(u) / in_scale) evaluated on the grid.
+static tk_status les_closure(tk_ns_t p, const tk_mlp *w, const void *u, hipStream_t s) {
+    const NsGrid &g = p->g;
+    const int n = g.n;
+    const long FS = (long)n * n * (n / 2 + 1);
+    const long M = (long)n * n * n;
+    LesWork &L = p->les;
+    hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)u, (float2 *)L.gsp, n);
+    TK_TRY(launch_check("gradient spectra"));
+    TK_TRY(fft_x_pass(g.ax, L.gsp, L.gsp, 9, 1, 1.0, s));
+    TK_TRY(fft_y_pass(g.ax, L.gsp, L.gsp, 9, 1, s));
+    TK_TRY(fft_z_c2r(g.ax, L.gsp, L.greal, 9, s));
+    TK_TRY(mlp_forward_run(w, L.greal, L.tau, M, s));
+    TK_TRY(fft_z_r2c(g.ax, L.tau, L.tauh, 6, 1.0, s));
+    TK_TRY(fft_y_pass(g.ax, L.tauh, L.tauh, 6, 0, s));
+    TK_TRY(fft_x_pass(g.ax, L.tauh, L.tauh, 6, 0, 1.0 / (double)M, s));
+    hipLaunchKernelGGL(k_sgs_div, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)L.tauh, (float2 *)L.add3, n);
+    return launch_check("stress divergence");
+}
+
+static tk_status les_steps(tk_ns_t p, const tk_mlp *w, void *u, int nsteps, hipStream_t s) {
+    const NsGrid &g = p->g;
+    P5Args a{};
+    a.u = u;
+    a.aux = p->aux;
+    a.ust = p->ust;
+    a.st = p->st;
+    a.nu = p->cfg.nu;
+    for (int k = 0; k < nsteps; ++k) {
+        if (w) TK_TRY(les_closure(p, w, u, s));
+        a.add3 = w ? p->les.add3 : nullptr;
+        a.mode = RK2_S1;
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        if (w) TK_TRY(les_closure(p, w, p->ust, s));
+        a.mode = RK2_S2;
+        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+    }
+    return TK_OK;
+}
+
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" tk_status sgs_mlp_forward(const tk_mlp *w, const float *x9, float *y6, long M, void *stream) {
+    TK_TRY(mlp_check(w));
+    if (!x9 || !y6 || M < 0) return fail(TK_EINVAL, "bad arguments");
+    if (M == 0) return TK_OK;
+    return mlp_forward_run(w, x9, y6, M, (hipStream_t)stream);
+}
+
+extern "C" tk_status sgs_mlp_backward(const tk_mlp *w, const float *x9, const float *dy6, long M, float *grad,
+                                      void *stream) {
+    TK_TRY(mlp_check(w));
+    if (!x9 || !dy6 || !grad || M <= 0) return fail(TK_EINVAL, "bad arguments");
+    return mlp_backward_run(w, x9, nullptr, dy6, M, grad, nullptr, (hipStream_t)stream);
+}
+
+extern "C" tk_status sgs_mlp_loss_grad(const tk_mlp *w, const float *x9, const float *t6, long M, float *grad,
+                                       double *loss, void *stream) {
+    TK_TRY(mlp_check(w));
+    if (!x9 || !t6 || !grad || M <= 0) return fail(TK_EINVAL, "bad arguments");
+    return mlp_backward_run(w, x9, t6, nullptr, M, grad, loss, (hipStream_t)stream);
+}
+
+extern "C" tk_status sgs_adam_step(tk_adam *opt, const float *grad, uint16_t *w_bf16, void *stream) {
+    if (!opt || !opt->w || !opt->m || !opt->v || !grad || !w_bf16) return fail(TK_EINVAL, "NULL argument");
+    if (!(opt->lr > 0) || !(opt->beta1 >= 0 && opt->beta1 < 1) || !(opt->beta2 >= 0 && opt->beta2 < 1))
+        return fail(TK_EINVAL, "bad Adam hyper-parameters");
+    opt->step += 1;
+    const float c1 = (float)(1.0 - std::pow((double)opt->beta1, opt->step));
+    const float c2 = (float)(1.0 - std::pow((double)opt->beta2, opt->step));
+    hipLaunchKernelGGL(k_adam, dim3(cdiv(NP, 256)), dim3(256), 0, (hipStream_t)stream, opt->w, opt->m, opt->v, grad,
+                       w_bf16, opt->lr, opt->beta1, opt->beta2, opt->eps, c1, c2);
+    return launch_check("adam");
+}
+
+extern "C" tk_status sgs_weights_to_bf16(const float *w, uint16_t *w_bf16, int n, void *stream) {
+    if (!w || !w_bf16 || n < 0) return fail(TK_EINVAL, "bad arguments");
+    if (n == 0) return TK_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv(n, 256)), dim3(256), 0, (hipStream_t)stream, w, w_bf16, n);
+    return launch_check("to bf16");
+}
+
+extern "C" tk_status les_step(tk_ns_t p, const tk_mlp *w, void *u, double dt, int nsteps, double *t_inout,
+                              int *fallback, void *stream) {
+    if (!p || !u) return fail(TK_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(TK_EINVAL, "nsteps must be >= 0");
+    if (p->cfg.dtype != TK_F32 || p->cfg.scheme != 0) return fail(TK_EUNSUPPORTED, "LES runs FP32 IF-RK2");
+    if (p->cfg.cfl <= 0 && !(dt > 0 && std::isfinite(dt))) return fail(TK_EINVAL, "dt must be > 0 without CFL");
+    hipStream_t s = (hipStream_t)stream;
+    int fb = 0;
+    const tk_mlp *model = w;
+    if (model) {
+        TK_TRY(mlp_check(model));
+        // weights that are not finite: plain DNS right-hand side
+        int *cnt = (int *)p->dscratch;
+        TK_HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(cdiv(NP, 256)), dim3(256), 0, s, model->w, NP, cnt);
+        TK_TRY(launch_check("weight check"));
+        int h = 0;
+        TK_HIP_CHECK(hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        TK_HIP_CHECK(hipStreamSynchronize(s));
+        if (h) {
+            model = nullptr;
+            fb = 1;
+        }
+    }
+    TK_TRY(les_work_alloc(p));
+    NsState &h0 = p->hstage;
+    h0 = NsState{};
+    h0.t = t_inout ? *t_inout : 0.0;
+    h0.hfix = dt > 0 ? dt : 0.0;
+    h0.cfl_dx = p->cfg.cfl > 0 ? p->cfg.cfl * 2.0 * M_PI / p->cfg.n : 0.0;
+    h0.h = h0.hfix;
+    TK_HIP_CHECK(hipMemcpyAsync(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+    TK_HIP_CHECK(hipMemcpyAsync(p->les.backup, u, 3 * p->fbytes, hipMemcpyDeviceToDevice, s));
+    TK_TRY(les_steps(p, model, u, nsteps, s));
+    if (model) {
+        // a state that left the finite numbers: redo the steps with the plain right-hand side
+        std::vector<double> hd(NS_DIAG_HEAD + p->nshell);
+        TK_TRY(ns_diag_run(u, p->g.n, TK_F32, p->nshell, p->dscratch, hd.data(), s));
+        if (!std::isfinite(hd[0])) {
+            fb = 2;
+            TK_HIP_CHECK(hipMemcpyAsync(u, p->les.backup, 3 * p->fbytes, hipMemcpyDeviceToDevice, s));
+            TK_HIP_CHECK(hipMemcpyAsync(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+            TK_TRY(les_steps(p, nullptr, u, nsteps, s));
+        }
+    }
+    NsState hf{};
+    TK_HIP_CHECK(hipMemcpyAsync(&hf, p->st, sizeof(hf), hipMemcpyDeviceToHost, s));
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    if (t_inout) *t_inout = hf.t;
+    p->last_dt = hf.h;
+    if (fallback) *fallback = fb;
+    return TK_OK;
+}
+
+// Filtered-DNS training data (see tk.h).
+extern "C" tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, int kc, float *grad9, float *tau6,
+                                    void *ubar_hat, void *stream) {
+    if (!uhat_dns || !grad9 || !tau6) return fail(TK_EINVAL, "NULL argument");
+    if (!supported_len(n_dns) || !supported_len(n_les) || n_les > n_dns)
+        return fail(TK_EUNSUPPORTED, "grids %d -> %d not supported", n_dns, n_les);
+    if (kc < 0 || 3 * kc >= n_les) return fail(TK_EINVAL, "cutoff kc=%d must satisfy 3 kc < n_les", kc);
+    hipStream_t s = (hipStream_t)stream;
+    FftAxes A, B;
+    TK_TRY(axes_init(&A, n_dns, n_dns, n_dns, TK_F32, true));
+    TK_TRY(axes_init(&B, n_les, n_les, n_les, TK_F32, true));
+    const long FD = (long)n_dns * n_dns * (n_dns / 2 + 1), FL = (long)n_les * n_les * (n_les / 2 + 1);
+    const long MD = (long)n_dns * n_dns * n_dns, ML = (long)n_les * n_les * n_les;
+    void *ud = nullptr, *cd = nullptr, *wsd = nullptr, *prod = nullptr, *ubh = nullptr, *gl = nullptr, *gsp = nullptr,
+         *ubr = nullptr, *guu = nullptr;
+    auto cleanup = [&]() {
+        void *ps[] = {ud, cd, wsd, prod, ubh, gl, gsp, ubr, guu};
+        for (void *q : ps)
+            if (q) hipFree(q);
+    };
+#define TK_ALLOC(ptr, bytes)                                                     \
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {                                  \
+        cleanup();                                                               \
+        return fail(TK_ENOMEM, "filter workspace allocation failed");            \
+    }
+    TK_ALLOC(ud, sizeof(float) * 3 * MD);          // u on the DNS grid
+    TK_ALLOC(cd, sizeof(float2) * FD);             // one DNS spectral field
+    TK_ALLOC(wsd, sizeof(float2) * FD);            // c2r workspace
+    TK_ALLOC(prod, sizeof(float) * MD);            // one product field
+    TK_ALLOC(ubh, sizeof(float2) * 3 * FL);        // filtered velocity spectrum
+    TK_ALLOC(gl, sizeof(float2) * 6 * FL);         // filtered products spectrum
+    TK_ALLOC(gsp, sizeof(float2) * 9 * FL);        // gradient spectra
+    TK_ALLOC(ubr, sizeof(float) * 3 * ML);         // filtered velocity, real
+    TK_ALLOC(guu, sizeof(float) * 6 * ML);         // filtered products, real
+#undef TK_ALLOC
+    tk_status st = TK_OK;
+    do {
+        // u on the DNS grid (input preserved: inverse through a workspace copy)
+        for (int c = 0; c < 3 && st == TK_OK; ++c) {
+            st = fft_x_pass(A, (const float2 *)uhat_dns + c * FD, wsd, 1, 1, 1.0, s);
+            if (st == TK_OK) st = fft_y_pass(A, wsd, wsd, 1, 1, s);
+            if (st == TK_OK) st = fft_z_c2r(A, wsd, (float *)ud + c * MD, 1, s);
+        }
+        if (st != TK_OK) break;
+        // G(u_i u_j): product on the DNS grid, r2c, truncation onto the coarse grid
+        const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
+        for (int q = 0; q < 6 && st == TK_OK; ++q) {
+            hipLaunchKernelGGL(k_mul, dim3(ew_blocks(MD)), dim3(256), 0, s, (const float *)ud + pi[q] * MD,
+                               (const float *)ud + pj[q] * MD, (float *)prod, MD);
+            st = launch_check("product");
+            if (st == TK_OK) st = fft_z_r2c(A, prod, cd, 1, 1.0, s);
+            if (st == TK_OK) st = fft_y_pass(A, cd, cd, 1, 0, s);
+            if (st == TK_OK) st = fft_x_pass(A, cd, cd, 1, 0, 1.0 / (double)MD, s);
+            if (st == TK_OK) {
+                hipLaunchKernelGGL(k_truncate, dim3(ew_blocks(FL)), dim3(256), 0, s, (const float2 *)cd, n_dns,
+                                   (float2 *)gl + q * FL, n_les, kc, 1);
+                st = launch_check("truncate");
+            }
+        }
+        if (st != TK_OK) break;
+        // filtered velocity and its gradients on the coarse grid
+        hipLaunchKernelGGL(k_truncate, dim3(ew_blocks(3 * FL)), dim3(256), 0, s, (const float2 *)uhat_dns, n_dns,
+                           (float2 *)ubh, n_les, kc, 3);
+        if ((st = launch_check("truncate u")) != TK_OK) break;
+        if (ubar_hat) TK_HIP_CHECK(hipMemcpyAsync(ubar_hat, ubh, sizeof(float2) * 3 * FL, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FL)), dim3(256), 0, s, (const float2 *)ubh, (float2 *)gsp,
+                           n_les);
+        if ((st = launch_check("gradient spectra")) != TK_OK) break;
+        if ((st = fft_x_pass(B, gsp, gsp, 9, 1, 1.0, s)) != TK_OK) break;
+        if ((st = fft_y_pass(B, gsp, gsp, 9, 1, s)) != TK_OK) break;
+        if ((st = fft_z_c2r(B, gsp, grad9, 9, s)) != TK_OK) break;
+        // ubar and G(u_i u_j) in real space, then tau
+        if ((st = fft_x_pass(B, ubh, ubh, 3, 1, 1.0, s)) != TK_OK) break;
+        if ((st = fft_y_pass(B, ubh, ubh, 3, 1, s)) != TK_OK) break;
+        if ((st = fft_z_c2r(B, ubh, ubr, 3, s)) != TK_OK) break;
+        if ((st = fft_x_pass(B, gl, gl, 6, 1, 1.0, s)) != TK_OK) break;
+        if ((st = fft_y_pass(B, gl, gl, 6, 1, s)) != TK_OK) break;
+        if ((st = fft_z_c2r(B, gl, guu, 6, s)) != TK_OK) break;
+        hipLaunchKernelGGL(k_tau, dim3(ew_blocks(ML)), dim3(256), 0, s, (const float *)guu, (const float *)ubr, tau6,
+                           ML);
+        st = launch_check("tau");
+    } while (0);
+    if (st == TK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(TK_EHIP, "filter synchronisation failed");
+    cleanup();
+    return st;
+}

@@ -103,22 +103,8 @@ tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, doubl
 
 using namespace tk;
 
-struct tk_ns_s {
-    ns_config cfg;
-    NsGrid g;
-    size_t fbytes;  // one spectral field
-    void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
-    NsState *st = nullptr;
-    double *dscratch = nullptr;
-    int nshell = 0;
-    double last_dt = 0;
-    NsState hstage{};  // host staging copy of the step state (outlives async copies)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    void *graph_u = nullptr;
-};
-
 static void ns_free(tk_ns_s *p) {
+    les_work_free(p->les);
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->w6) hipFree(p->w6);

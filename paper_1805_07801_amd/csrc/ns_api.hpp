@@ -36,4 +36,34 @@ tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &
 tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, double energy, double *dscratch,
                               hipStream_t s);
 
+// Workspace of the learned-closure LES (allocated on first use by les_step).
+struct LesWork {
+    void *gsp = nullptr;   // 9 spectral gradient fields
+    float *greal = nullptr;  // [9][n^3] gradients
+    float *tau = nullptr;    // [6][n^3] stress
+    void *tauh = nullptr;  // 6 spectral stress fields
+    void *add3 = nullptr;  // 3 spectral fields: -i k_j tau^_ij
+    void *backup = nullptr;  // 3 spectral fields: state at entry (fallback)
+};
+
+void les_work_free(LesWork &w);
+
 }  // namespace tk
+
+struct tk_ns_s {
+    ns_config cfg;
+    tk::NsGrid g;
+    size_t fbytes;  // one spectral field
+    void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
+    tk::NsState *st = nullptr;
+    double *dscratch = nullptr;
+    int nshell = 0;
+    double last_dt = 0;
+    tk::NsState hstage{};  // host staging copy of the step state (outlives async copies)
+    tk::LesWork les;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    void *graph_u = nullptr;
+};
+
+

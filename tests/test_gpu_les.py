@@ -1,0 +1,129 @@
+"""Learned closure on the GPU against the FP64 oracle: network forward / gradients / Adam,
+filtered-DNS training data, the LES step and its fallbacks."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import diag, fft as offt, init as oinit, les as oles, mlp as omlp, ns as ons
+
+pytestmark = pytest.mark.gpu
+
+
+def theta0(seed=0, scale=1.0):
+    Ws, bs = synth.mlp_init(seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    bs = [rng.standard_normal(b.shape) * 0.1 for b in bs]
+    return omlp.bf16_round(omlp.pack([W * scale for W in Ws], bs))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def test_bf16_copy_matches_oracle_rounding(tk):
+    rng = np.random.default_rng(0)
+    th = rng.standard_normal(5190) * 3
+    th[:4] = [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 1e-30]
+    net = tk.Closure(th)
+    assert np.array_equal(net.bf16_bits(), omlp.bf16_bits(th))
+
+
+@pytest.mark.parametrize("M", [1, 255, 4096, 100003])
+def test_forward_vs_oracle(tk, M):
+    import torch
+    th = theta0(2)
+    x = np.random.default_rng(M).standard_normal((9, M)).astype(np.float32) * 2.0
+    net = tk.Closure(th, in_scale=2.0, out_scale=0.5)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = 0.5 * omlp.forward(th, x.astype(np.float64) / 2.0)
+    assert rel(y, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("M", [300, 65536])
+def test_loss_and_gradient_vs_oracle(tk, M):
+    import torch
+    th = theta0(3)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((9, M)).astype(np.float32)
+    t = rng.standard_normal((6, M)).astype(np.float32)
+    net = tk.Closure(th, in_scale=1.5, out_scale=2.0)
+    loss = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = net.grad.cpu().numpy()
+    y = omlp.forward(th, x.astype(np.float64) / 1.5)
+    Lref, dy = omlp.mse_loss(y, t.astype(np.float64) / 2.0)
+    gref = omlp.backward(th, x.astype(np.float64) / 1.5, dy)
+    assert abs(loss - Lref) <= 1e-5 * Lref
+    assert rel(g, gref) <= 1e-4
+    # generic backward with a given upstream gradient
+    dyr = rng.standard_normal((6, M)).astype(np.float32)
+    g2 = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(dyr).cuda()).cpu().numpy()
+    assert rel(g2, omlp.backward(th, x.astype(np.float64) / 1.5, dyr.astype(np.float64))) <= 1e-4
+
+
+def test_adam_steps_vs_oracle(tk):
+    import torch
+    th = theta0(4)
+    rng = np.random.default_rng(1)
+    net = tk.Closure(th, lr=1e-3)
+    w, m, v = th.copy(), np.zeros(5190), np.zeros(5190)
+    for k in range(1, 4):
+        g = rng.standard_normal(5190).astype(np.float32)
+        net.grad.copy_(torch.from_numpy(g))
+        net.adam_step()
+        w, m, v = omlp.adam(w, m, v, g.astype(np.float64), k, 1e-3)
+    assert net.opt.step == 3
+    assert np.max(np.abs(net.w32.cpu().numpy() - w)) <= 1e-6
+    assert np.array_equal(net.bf16_bits(), omlp.bf16_bits(net.w32.cpu().numpy()))
+
+
+def test_filter_dns_vs_oracle(tk):
+    import torch
+    n_dns, n_les, kc = 128, 64, 21
+    # white-noise solenoidal field: plenty of energy above the cutoff, so tau = O(1)
+    noise = synth.gaussian_field((3, n_dns, n_dns, n_dns), 5).astype(np.float64)
+    u = ons.project(offt.rfft3(noise) * ons.dealias_mask(n_dns))
+    u /= np.sqrt(diag.energy(u))
+    g, t, ub = tk.les_filter_dns(torch.from_numpy(u.astype(np.complex64)).cuda(), n_les, kc, with_ubar=True)
+    ubar = oles.filtered_velocity(u, n_les, kc)
+    assert diag.rel_l2(ub.cpu().numpy(), ubar, n_les) <= 1e-6
+    gref = oles.gradients(ubar).reshape(9, -1)
+    assert rel(g.cpu().numpy(), gref) <= 1e-5
+    tref = oles.sgs_stress(u, n_les, kc).reshape(6, -1)
+    assert rel(t.cpu().numpy(), tref) <= 1e-4
+
+
+def test_les_step_vs_oracle_and_fallback(tk):
+    import torch
+    n = 32
+    nu, h = 5e-3, 0.004
+    u0 = oinit.random_solenoidal(synth.gaussian_field((3, n, n, n), 9))
+    th = theta0(5, scale=0.3)
+    s_in, s_out = 3.0, 0.05
+    net = tk.Closure(th, in_scale=s_in, out_scale=s_out)
+    s = tk.NS(n, dtype=torch.float32, nu=nu)
+    ud = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    t, fb = tk.les_step(s, net, ud, h, 1)
+    assert fb == 0 and abs(t - h) < 1e-15
+    ref = ons.ifrk2_step(u0, nu, h, rhs_fn=lambda v: oles.les_rhs(v, th, s_in, s_out))[0]
+    assert diag.rel_l2(ud.cpu().numpy(), ref, n) <= 1e-4
+    # the model changes the step (the parity above is not the no-model path)
+    plain = ons.ifrk2_step(u0, nu, h)[0]
+    assert diag.rel_l2(ref, plain, n) > 1e-6
+    # no model: identical to the plain solver step
+    ua = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    ub = ua.clone()
+    tk.les_step(s, None, ua, h, 2)
+    s.step(ub, h, 2)
+    assert torch.equal(ua, ub)
+    # non-finite weights: fallback to the plain right-hand side
+    bad = th.copy()
+    bad[100] = np.nan
+    netb = tk.Closure(bad, in_scale=s_in, out_scale=s_out)
+    uc = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    _, fb = tk.les_step(s, netb, uc, h, 2)
+    assert fb == 1 and torch.equal(uc, ub)
+    # a model that blows the state up: restored and redone without the model
+    huge = tk.Closure(th, in_scale=s_in, out_scale=3e38)
+    ud2 = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    _, fb = tk.les_step(s, huge, ud2, h, 2)
+    assert fb == 2 and torch.equal(ud2, ub)
