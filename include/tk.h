@@ -50,6 +50,10 @@ const char *tk_last_error(void);
 /* ABI version (major * 10000 + minor * 100 + patch). */
 int tk_version(void);
 
+/* *out = sum of x_i^2 over n real values (device, dtype dt), accumulated in FP64 with a
+ * fixed reduction order.  Synchronises stream. */
+tk_status tk_sum_squares(const void *x, long n, tk_dtype dt, double *out, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * 3D FFT in the Fourier (FFF) basis.
  * Paper, Section "Fast Fourier Transform": the inverse transform is the plain sum
@@ -267,8 +271,10 @@ tk_status les_step(tk_ns_t ns, const tk_mlp *w_or_null, void *uhat_inout, double
 
 /* Training data from a DNS state uhat_dns [3][n_dns][n_dns][n_dns/2+1] (FP32, not
  * modified): box filter |k_i| <= kc (3 kc < n_les), truncated onto the n_les grid:
- * grad9 [9][n_les^3] = d_j ubar_i, tau6 [6][n_les^3] = G(u_i u_j) - ubar_i ubar_j with the
- * first product formed on the DNS grid, and optionally ubar_hat [3][n_les][n_les][n_les/2+1].
+ * grad9 [9][n_les^3] = d_j ubar_i, tau6 [6][n_les^3] = G(u_i u_j) - G(ubar_i ubar_j) (the
+ * stress the dealiased LES lacks: its own nonlinear term is G(ubar_i ubar_j)), the first
+ * product formed on the DNS grid and the second on the LES grid, and optionally
+ * ubar_hat [3][n_les][n_les][n_les/2+1].
  * Allocates and frees its own workspace (about 6 DNS fields).  Synchronises. */
 tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, int kc, float *grad9, float *tau6,
                          void *ubar_hat, void *stream);

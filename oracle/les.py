@@ -4,9 +4,10 @@ infrastructure).
 Readings (stated in the design notes): the filter G is the sharp spectral box
 |k_i| <= kc, applied by truncating the DNS spectrum onto the coarse grid (kc = (n-1)/3,
 the coarse grid's 2/3 set, so the filtered field is exactly representable there);
-tau_ij = G(u_i u_j) - ubar_i ubar_j with the first product formed on the DNS grid and
-the second pointwise on the coarse grid; features are the nine filtered gradients
-d_j ubar_i on the coarse grid.  The LES right-hand side adds -i k_j tau^_ij to the
+tau_ij = G(u_i u_j) - G(ubar_i ubar_j): the stress the dealiased LES lacks, since its
+own nonlinear term is exactly G(ubar_i ubar_j).  The first product is formed on the
+DNS grid; the second on the coarse grid, where the 2/3 rule makes its kept modes exact.
+Features are the nine filtered gradients d_j ubar_i on the coarse grid.  The LES right-hand side adds -i k_j tau^_ij to the
 nonlinear term before masking and projection.
 """
 import numpy as np
@@ -47,13 +48,14 @@ def gradients(ubar_hat):
 
 
 def sgs_stress(uhat_dns, n_les, kc):
-    """tau [6][n][n][n] on the coarse grid."""
+    """tau_ij = G(u_i u_j) - G(ubar_i ubar_j), [6][n][n][n] on the coarse grid."""
     u = fft.irfft3(uhat_dns)
     ubar = fft.irfft3(filtered_velocity(uhat_dns, n_les, kc))
     out = []
     for (i, j) in PAIRS:
         G = truncate(fft.rfft3(u[i] * u[j]), n_les, kc)
-        out.append(fft.irfft3(G) - ubar[i] * ubar[j])
+        Gb = truncate(fft.rfft3(ubar[i] * ubar[j]), n_les, kc)
+        out.append(fft.irfft3(G - Gb))
     return np.stack(out)
 
 

@@ -42,6 +42,7 @@ def _declare(L):
     sigs = {
         "tk_last_error": ([], ctypes.c_char_p),
         "tk_version": ([], i),
+        "tk_sum_squares": ([vp, ctypes.c_long, i, P(d), vp], i),
         "fft3d_plan_create": ([P(vp), i, i, i, i, i, u], i),
         "fft3d_workspace_size": ([vp, P(sz)], i),
         "fft3d_set_workspace": ([vp, vp], i),
@@ -121,6 +122,13 @@ def _dtype_code(dtype):
     if dtype in (torch.float64, torch.complex128):
         return TK_F64
     raise TkError(TK_EUNSUPPORTED, "dtype %s" % dtype)
+
+
+def sum_squares(x, stream=None):
+    """sum x_i^2 of a real GPU tensor, FP64 accumulation in the library."""
+    out = ctypes.c_double()
+    check(lib().tk_sum_squares(_ptr(x), x.numel(), _dtype_code(x.dtype), ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def autotune(nx, ny=None, nz=None, batch=1, dtype=None, iters=5):

@@ -298,6 +298,11 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
         b->bufs.push_back(w6);
         b->bufs.push_back(aux);
         b->bufs.push_back(ust);
+        // stage buffers start at zero: passes write only the 2/3-rule modes
+        if (hipMemset(aux, 0, 3 * fb) != hipSuccess || hipMemset(ust, 0, 3 * fb) != hipSuccess) {
+            nsb_free(b);
+            return fail(TK_EHIP, "ensemble workspace clear failed");
+        }
         BInst &d = b->hinst[i];
         d.n = n[i];
         d.K = b->grids[i].K;

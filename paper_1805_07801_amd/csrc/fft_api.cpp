@@ -286,3 +286,13 @@ extern "C" tk_status fft3d_plan_destroy(tk_fft3d_t p) {
     delete p;
     return TK_OK;
 }
+
+extern "C" tk_status tk_sum_squares(const void *x, long n, tk_dtype dt, double *out, void *stream) {
+    if (!x || !out || n < 0) return fail(TK_EINVAL, "bad arguments");
+    if (dt != TK_F32 && dt != TK_F64) return fail(TK_EUNSUPPORTED, "dtype");
+    if (n == 0) {
+        *out = 0;
+        return TK_OK;
+    }
+    return reduce_sumsq_real(x, n, dt, out, (hipStream_t)stream);
+}

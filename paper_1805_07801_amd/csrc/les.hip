@@ -261,8 +261,10 @@ __global__ void k_count_nonfinite(const uint16_t *__restrict__ wb, int n, int *_
 }
 
 // ---- spectral helpers ---------------------------------------------------------------------------------
-// g[3 i + j] = i k_j u^_i (Nyquist derivative taken as zero), 9 fields.
-__global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g, int N) {
+// g[3 i + j] = i k_j u^_i (Nyquist derivative taken as zero), 9 fields.  Only modes with
+// |kx|, |ky|, kz <= K are read (the others are zero in a 2/3-masked state, and the
+// solver's stage buffers leave them unwritten).
+__global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g, int N, int K) {
     const int NZH = N / 2 + 1;
     const long FS = (long)N * N * NZH;
     for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < FS; m += (long)gridDim.x * blockDim.x) {
@@ -271,9 +273,10 @@ __global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g
         const int y = (int)(xy % N), x = (int)(xy / N);
         const int k[3] = {2 * x == N ? 0 : (x < N / 2 ? x : x - N), 2 * y == N ? 0 : (y < N / 2 ? y : y - N),
                           2 * kz0 == N ? 0 : kz0};
+        const bool kept = abs(x < N / 2 ? x : x - N) <= K && abs(y < N / 2 ? y : y - N) <= K && kz0 <= K;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const float2 a = u[i * FS + m];
+            const float2 a = kept ? u[i * FS + m] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int j = 0; j < 3; ++j) g[(3 * i + j) * FS + m] = make_float2(-a.y * k[j], a.x * k[j]);
         }
@@ -329,12 +332,19 @@ __global__ void k_mul(const float *__restrict__ a, const float *__restrict__ b, 
         o[i] = a[i] * b[i];
 }
 
-// tau_q = G(u_i u_j) - ubar_i ubar_j, q over the 6 pairs.
-__global__ void k_tau(const float *__restrict__ guu, const float *__restrict__ ub, float *__restrict__ tau, long M) {
-    const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
-    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < M; p += (long)gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) tau[q * M + p] = guu[q * M + p] - ub[pi[q] * M + p] * ub[pj[q] * M + p];
+// a -= b on the modes |kx|, |ky|, kz <= kc of an n-grid half spectrum (one field).
+__global__ void k_sub_kept(const float2 *__restrict__ b, float2 *__restrict__ a, int n, int kc) {
+    const int h = n / 2 + 1;
+    const long F = (long)n * n * h;
+    for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < F; m += (long)gridDim.x * blockDim.x) {
+        const int kz = (int)(m % h);
+        const long xy = m / h;
+        const int y = (int)(xy % n), x = (int)(xy / n);
+        const int kx = x < n / 2 ? x : x - n, ky = y < n / 2 ? y : y - n;
+        if (abs(kx) <= kc && abs(ky) <= kc && kz <= kc) {
+            const float2 u = a[m], v = b[m];
+            a[m] = make_float2(u.x - v.x, u.y - v.y);
+        }
     }
 }
 
@@ -453,7 +463,7 @@ static tk_status les_closure(tk_ns_t p, const tk_mlp *w, const void *u, hipStrea
     const long FS = (long)n * n * (n / 2 + 1);
     const long M = (long)n * n * n;
     LesWork &L = p->les;
-    hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)u, (float2 *)L.gsp, n);
+    hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)u, (float2 *)L.gsp, n, g.K);
     TK_TRY(launch_check("gradient spectra"));
     TK_TRY(fft_x_pass(g.ax, L.gsp, L.gsp, 9, 1, 1.0, s));
     TK_TRY(fft_y_pass(g.ax, L.gsp, L.gsp, 9, 1, s));
@@ -617,9 +627,10 @@ extern "C" tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, 
     TK_ALLOC(gl, sizeof(float2) * 6 * FL);         // filtered products spectrum
     TK_ALLOC(gsp, sizeof(float2) * 9 * FL);        // gradient spectra
     TK_ALLOC(ubr, sizeof(float) * 3 * ML);         // filtered velocity, real
-    TK_ALLOC(guu, sizeof(float) * 6 * ML);         // filtered products, real
+    TK_ALLOC(guu, sizeof(float) * ML);             // one coarse product, real
 #undef TK_ALLOC
     tk_status st = TK_OK;
+    const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
     do {
         // u on the DNS grid (input preserved: inverse through a workspace copy)
         for (int c = 0; c < 3 && st == TK_OK; ++c) {
@@ -629,7 +640,6 @@ extern "C" tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, 
         }
         if (st != TK_OK) break;
         // G(u_i u_j): product on the DNS grid, r2c, truncation onto the coarse grid
-        const int pi[6] = {0, 1, 2, 0, 0, 1}, pj[6] = {0, 1, 2, 1, 2, 2};
         for (int q = 0; q < 6 && st == TK_OK; ++q) {
             hipLaunchKernelGGL(k_mul, dim3(ew_blocks(MD)), dim3(256), 0, s, (const float *)ud + pi[q] * MD,
                                (const float *)ud + pj[q] * MD, (float *)prod, MD);
@@ -650,21 +660,35 @@ extern "C" tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, 
         if ((st = launch_check("truncate u")) != TK_OK) break;
         if (ubar_hat) TK_HIP_CHECK(hipMemcpyAsync(ubar_hat, ubh, sizeof(float2) * 3 * FL, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FL)), dim3(256), 0, s, (const float2 *)ubh, (float2 *)gsp,
-                           n_les);
+                           n_les, kc);
         if ((st = launch_check("gradient spectra")) != TK_OK) break;
         if ((st = fft_x_pass(B, gsp, gsp, 9, 1, 1.0, s)) != TK_OK) break;
         if ((st = fft_y_pass(B, gsp, gsp, 9, 1, s)) != TK_OK) break;
         if ((st = fft_z_c2r(B, gsp, grad9, 9, s)) != TK_OK) break;
-        // ubar and G(u_i u_j) in real space, then tau
+        // tau = G(u_i u_j) - G(ubar_i ubar_j): ubar in real space on the coarse grid, its
+        // products (kept modes exact there by the 2/3 rule) subtracted in spectral space
         if ((st = fft_x_pass(B, ubh, ubh, 3, 1, 1.0, s)) != TK_OK) break;
         if ((st = fft_y_pass(B, ubh, ubh, 3, 1, s)) != TK_OK) break;
         if ((st = fft_z_c2r(B, ubh, ubr, 3, s)) != TK_OK) break;
+        for (int q = 0; q < 6 && st == TK_OK; ++q) {
+            float *pr = (float *)guu;  // coarse real product
+            float2 *pc = (float2 *)gsp;  // coarse spectral product
+            hipLaunchKernelGGL(k_mul, dim3(ew_blocks(ML)), dim3(256), 0, s, (const float *)ubr + pi[q] * ML,
+                               (const float *)ubr + pj[q] * ML, pr, ML);
+            st = launch_check("coarse product");
+            if (st == TK_OK) st = fft_z_r2c(B, pr, pc, 1, 1.0, s);
+            if (st == TK_OK) st = fft_y_pass(B, pc, pc, 1, 0, s);
+            if (st == TK_OK) st = fft_x_pass(B, pc, pc, 1, 0, 1.0 / (double)ML, s);
+            if (st == TK_OK) {
+                hipLaunchKernelGGL(k_sub_kept, dim3(ew_blocks(FL)), dim3(256), 0, s, (const float2 *)pc,
+                                   (float2 *)gl + q * FL, n_les, kc);
+                st = launch_check("subtract resolved product");
+            }
+        }
+        if (st != TK_OK) break;
         if ((st = fft_x_pass(B, gl, gl, 6, 1, 1.0, s)) != TK_OK) break;
         if ((st = fft_y_pass(B, gl, gl, 6, 1, s)) != TK_OK) break;
-        if ((st = fft_z_c2r(B, gl, guu, 6, s)) != TK_OK) break;
-        hipLaunchKernelGGL(k_tau, dim3(ew_blocks(ML)), dim3(256), 0, s, (const float *)guu, (const float *)ubr, tau6,
-                           ML);
-        st = launch_check("tau");
+        st = fft_z_c2r(B, gl, tau6, 6, s);
     } while (0);
     if (st == TK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(TK_EHIP, "filter synchronisation failed");
     cleanup();

@@ -141,7 +141,9 @@ extern "C" tk_status ns_create(tk_ns_t *out, const ns_config *cfg) {
         return fail(TK_ENOMEM, "solver workspace allocation (%zu bytes) failed", 12 * p->fbytes);
     }
     NsState h0{};
-    if (hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {
+    // stage buffers start at zero: passes write only the 2/3-rule modes
+    if (hipMemset(p->aux, 0, 3 * p->fbytes) != hipSuccess || hipMemset(p->ust, 0, 3 * p->fbytes) != hipSuccess ||
+        hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {
         ns_free(p);
         return fail(TK_EHIP, "state upload failed");
     }

@@ -108,6 +108,22 @@ def test_stress_of_single_high_mode():
     assert np.max(np.abs(tau[1:])) <= 1e-13
 
 
+def test_stress_filters_the_resolved_product():
+    """tau = G(u u) - G(ubar ubar): for a DNS field that is already filtered (|k_i| <= 21)
+    the stress vanishes even though ubar_i ubar_j itself has modes up to 42 (pointwise
+    products on the coarse grid are not subtracted unfiltered); the resolved product
+    G(ubar ubar) formed on the 64 grid equals the one formed on the finer DNS grid."""
+    n_dns, n_les, kc = 96, 64, 21
+    uh = band_limited_state(n_dns, 21, seed=6)
+    assert np.max(np.abs(les.sgs_stress(uh, n_les, kc))) <= 1e-13
+    ub = les.filtered_velocity(uh, n_les, kc)
+    u64 = fft.irfft3(ub)
+    u96 = fft.irfft3(uh)
+    a = les.truncate(fft.rfft3(u64[0] * u64[1]), n_les, kc)
+    b = les.truncate(fft.rfft3(u96[0] * u96[1]), n_les, kc)
+    assert np.max(np.abs(a - b)) <= 1e-15
+
+
 def test_gradient_features_taylor_green():
     n = 32
     uh = fft.rfft3(synth.taylor_green(n))
