@@ -39,6 +39,48 @@ def pair_flops(n):
     return 2 * 5 * n ** 3 * math.log2(n ** 3)
 
 
+def ensemble_rate(tk, torch, steps=10):
+    """The 48-member ensemble (16 x 64^3, 16 x 96^3, 16 x 128^3, CFL 0.5): member-steps/s
+    and grid-point-steps/s, one HIP-graph launch per ensemble step."""
+    import synth
+    sizes = synth.ensemble_sizes()
+    ens = tk.Ensemble(sizes, synth.ensemble_viscosities(), cfl=0.5)
+    st = [ens.init_random(i, torch.from_numpy(synth.gaussian_field((3, m, m, m), synth.ensemble_seed(i))).cuda())
+          for i, m in enumerate(sizes)]
+    ens.step(st, 0.0, 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ens.step(st, 0.0, steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    pts = sum(m ** 3 for m in sizes)
+    ens.close()
+    return {"ensemble_steps_per_s": round(1 / dt, 2), "member_steps_per_s": round(len(sizes) / dt, 1),
+            "point_steps_per_s": round(pts / dt, 1)}
+
+
+def les_rate(tk, torch, steps=50):
+    """64^3 LES steps/s with a closure network (random weights: the cost does not depend
+    on them) and without."""
+    import numpy as np
+    import synth
+    Ws, bs = synth.mlp_init(seed=7)
+    theta = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in zip(Ws, bs)])
+    net = tk.Closure(theta, in_scale=2.0, out_scale=1e-3)
+    ns = tk.NS(64, dtype=torch.float32, nu=1e-3)
+    u = ns.init_random(torch.from_numpy(synth.gaussian_field((3, 64, 64, 64), 3)).cuda())
+    out = {}
+    for name, model in (("les64_closure_steps_per_s", net), ("les64_plain_steps_per_s", None)):
+        tk.les_step(ns, model, u, 1e-3, 2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tk.les_step(ns, model, u, 1e-3, steps)
+        torch.cuda.synchronize()
+        out[name] = round(steps / (time.perf_counter() - t), 1)
+    ns.close()
+    return out
+
+
 def time_pairs(tk, torch, n, steps, warmup, seed=0):
     import numpy as np
     import synth
@@ -75,6 +117,23 @@ def time_pairs(tk, torch, n, steps, warmup, seed=0):
     return ms, passes, desc, err
 
 
+def kernel_names(desc, n):
+    """Template names of the six pass kernels from the plan's tile descriptions."""
+    import re
+    z = re.search(r"LPW=(\d+) E=(\d+)", desc[0])
+    y = re.search(r"W=(\d+) E=(\d+)", desc[1])
+    x = re.search(r"W=(\d+) E=(\d+)", desc[2])
+    names = {}
+    if z:
+        names["z_r2c"] = "k_z_r2c<float, %d, %s, %s>" % (n // 2, z.group(2), z.group(1))
+        names["z_c2r"] = "k_z_c2r<float, %d, %s, %s>" % (n // 2, z.group(2), z.group(1))
+    if y:
+        names["y_fwd"] = names["y_inv"] = "k_strided<float, %d, %s, %s>" % (n, y.group(2), y.group(1))
+    if x:
+        names["x_fwd"] = names["x_inv"] = "k_strided<float, %d, %s, %s>" % (n, x.group(2), x.group(1))
+    return names
+
+
 def roofline(n, passes):
     pb = pass_bytes(n)
     dom = max(passes, key=lambda k: passes[k])
@@ -90,6 +149,53 @@ def roofline(n, passes):
         "kernel_ms": round(passes[dom], 4),
         "bytes_per_launch": pb[dom],
     }
+
+
+def copy_bandwidth(torch, nbytes=1 << 29, reps=20):
+    """Measured device copy bandwidth (read + write bytes / time) of a plain copy kernel on
+    a 512 MiB buffer: the practical ceiling the passes are compared with."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def traffic_from_profile(kernel_name):
+    """HBM bytes per launch of the named kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
+    None if the summary does not cover this kernel or the kernel sources changed since."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "fft3d_pair_512_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    src = b""
+    for f in ("fft_core.hpp", "fft_kernels.hpp"):
+        with open(os.path.join(here, "paper_1805_07801_amd", "csrc", f), "rb") as fh:
+            src += fh.read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 3 and parts[0] == "source_digest":
+                rec["digest"] = parts[1]
+            if len(parts) >= 3 and parts[0] == "traffic_bytes_per_launch":
+                rec[parts[1]] = float(parts[2])
+    if rec.get("digest") != digest:
+        return None
+    return rec.get(kernel_name)
 
 
 def cpu_baseline(n=512):
@@ -140,6 +246,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--no-1024", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the ensemble and LES measurements")
+    ap.add_argument("--retune", action="store_true", help="autotune instead of using the committed cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU (slab all-to-all) path is design-only "
@@ -151,12 +259,18 @@ def main():
     tk.load()
     n = 512
     R, C = field_bytes(n)
-    # the library's autotuner picks the tile shapes of each pass (untimed)
-    for nn in ((512,) if args.no_1024 else (512, 1024)):
-        tk.autotune(nn, iters=3)
+    # tile shapes: the committed autotuner cache for this GPU, else a fresh autotune (untimed)
+    from paper_1805_07801_amd import tune
+    if args.retune or tune.load_default() == 0:
+        for nn in ((512,) if args.no_1024 else (512, 1024)):
+            tk.autotune(nn, iters=3)
+    copy_gbps = copy_bandwidth(torch)
     ms, passes, desc, err = time_pairs(tk, torch, n, args.steps, args.warmup)
     value = (2 * R + 10 * C) / (ms * 1e-3) / 1e9
     dom, roof = roofline(n, passes)
+    kname = kernel_names(desc, n).get(dom)
+    roof["kernel_name"] = kname
+    roof["traffic"] = traffic_from_profile(kname) if kname else None
     pb = pass_bytes(n)
     out = {
         "metric": "3D FFT pair GB/s & %HBM peak at 512^3/1024^3 FP32; NS RK2 steps/sec",
@@ -174,6 +288,8 @@ def main():
         "config": {"workload": "fft3d_pair_512", "n": n, "batch": 1, "input": "N(0,1) seed 0",
                    "step": "forward r2c + inverse c2r"},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
+        "copy_GBps_measured": round(copy_gbps, 1),
+        "pct_of_measured_copy": round(100 * value / copy_gbps, 2),
         "compulsory_GBps": round(2 * (R + C) / (ms * 1e-3) / 1e9, 1),
         "gflops_paper_convention": round(pair_flops(n) / (ms * 1e-3) / 1e9, 1),
         "roundtrip_rel_l2": err,
@@ -200,6 +316,11 @@ def main():
         sps, e = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 5), 2)
         out["ns512_rk2_steps_per_s"] = round(sps, 2)
         out["ns512_energy_after"] = e
+    if not args.no_extra:
+        out.update(ensemble_rate(tk, torch))
+        out.update(les_rate(tk, torch))
+        if "ns512_rk2_steps_per_s" in out:
+            out["les64_over_dns512_speed"] = round(out["les64_closure_steps_per_s"] / out["ns512_rk2_steps_per_s"], 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(512)
     print(json.dumps(out))

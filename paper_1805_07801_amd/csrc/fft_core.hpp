@@ -190,6 +190,31 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
     }
 }
 
+// ---- mirror exchange ---------------------------------------------------------------------------------
+// The real-FFT split and merge need x[(L - k) mod L] next to x[k].  With thread jt of a
+// line holding x[jt + i TPL], that value sits in thread (TPL - jt) mod TPL, register
+// E - 1 - i (jt > 0), or in the thread itself, register (E - i) mod E (jt = 0).  A line's
+// TPL threads are consecutive lanes of one wavefront (TPL divides 64), so a cross-lane
+// shuffle fetches it without LDS or barriers.
+template <typename T, int L, int E>
+__device__ __forceinline__ void mirror(const V2<T> (&v)[E], V2<T> (&m)[E], int jt) {
+    constexpr int TPL = L / E;
+    static_assert(TPL <= 64 && (64 % TPL) == 0, "a line must sit inside one wavefront");
+    const int lane = threadIdx.x & 63;
+    const int src = lane - jt + ((TPL - jt) & (TPL - 1));
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        V2<T> p;
+        if constexpr (TPL > 1) {
+            p.x = __shfl(v[E - 1 - i].x, src, 64);
+            p.y = __shfl(v[E - 1 - i].y, src, 64);
+        } else {
+            p = v[E - 1 - i];
+        }
+        m[i] = (jt != 0) ? p : v[(E - i) % E];
+    }
+}
+
 // Cooperative copy of a twiddle table of n entries into LDS; the caller places a
 // barrier before its first use.
 template <typename T>

@@ -155,18 +155,16 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_z_r2c(const T *__restrict__ sr
     __syncthreads();
     C *d = lds + ln * LL;
     line_fft<T, L, E, 1, 2>(v, d, jt, tw);
-#pragma unroll
-    for (int i = 0; i < E; ++i) d[lds_at<1>(jt + i * TPL)] = v[i];
-    __syncthreads();
+    C zm[E];
+    mirror<T, L, E>(v, zm, jt);
     if (valid) {
         C *o = dst + l * NZH;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
             const C zk = v[i];
-            const C zm = cconj(d[lds_at<1>((L - k) % L)]);
-            const C a = cadd(zk, zm);
-            const C b = cmul(tw[k], csub(zk, zm));
+            const C a = cadd(zk, cconj(zm[i]));
+            const C b = cmul(tw[k], csub(zk, cconj(zm[i])));
             C x;
             x.x = (T)0.5 * (a.x + b.y) * scale;
             x.y = (T)0.5 * (a.y - b.x) * scale;
@@ -192,20 +190,24 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_z_c2r(const V2<T> *__restrict_
     const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
     const bool valid = l < nlines;
     const C *s = src + (valid ? l : 0) * NZH;
-    C v[E];
+    C v[E], xm[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = valid ? s[jt + i * TPL] : mk<T>(0, 0);
+    const C xl = (valid && jt == 0) ? s[L] : mk<T>(0, 0);  // Nyquist entry X[L]
     load_twiddles<T>(tw, twg, 2 * L, tid, NT);
+    mirror<T, L, E>(v, xm, jt);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int k = jt + i * TPL;
-        C xk = valid ? s[k] : mk<T>(0, 0);
-        C xm = valid ? cconj(s[L - k]) : mk<T>(0, 0);
+        C xk = v[i];
+        C xc = cconj(k == 0 ? xl : xm[i]);
         if (k == 0) {
             xk.y = 0;
-            xm.y = 0;
+            xc.y = 0;
         }
-        const C a = cadd(xk, xm);
-        const C b = cmul(cconj(tw[k]), csub(xk, xm));
+        const C a = cadd(xk, xc);
+        const C b = cmul(cconj(tw[k]), csub(xk, xc));
         v[i] = mk<T>(a.x - b.y, -(a.y + b.x));  // conj(Z')
     }
     C *d = lds + ln * LL;

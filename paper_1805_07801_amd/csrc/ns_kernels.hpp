@@ -146,45 +146,59 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     const long l = tile * LPW + ln;
     const bool valid = l < nlines;
     C *d = lds + ln * LL;
-    // real-space samples: r[f][i] = (x[2n], x[2n+1]) at n = jt + i TPL
-    C r[6][E];
+    // real-space samples, packed pairs (x[2n], x[2n+1]) at n = jt + i TPL: u is kept, the
+    // three vorticity components are folded into c = u x omega as they arrive
+    C uu[3][E], c[3][E];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const C *s = w6 + f * FS + (valid ? l : 0) * NZH;
-        C v[E];
+        C v[E], xm[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
-            C xk = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
-            C xm = (valid && L - k < KZC) ? cconj(s[L - k]) : mk<T>(0, 0);
-            if (k == 0) {
-                xk.y = 0;
-                xm.y = 0;
-            }
-            const C a = cadd(xk, xm);
-            const C b = cmul(cconj(tw[k]), csub(xk, xm));
+            v[i] = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
+        }
+        // X[L - k] from the mirror lane (X[L] itself is a masked mode: zero)
+        mirror<T, L, E>(v, xm, jt);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int k = jt + i * TPL;
+            C xk = v[i];
+            C xc = k == 0 ? mk<T>(0, 0) : cconj(xm[i]);
+            if (k == 0) xk.y = 0;
+            const C a = cadd(xk, xc);
+            const C b = cmul(cconj(tw[k]), csub(xk, xc));
             v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
         }
         line_fft<T, L, E, 1, 2>(v, d, jt, tw);
 #pragma unroll
-        for (int i = 0; i < E; ++i) r[f][i] = mk<T>(v[i].x, -v[i].y);
-    }
-    // c = u x omega, both samples of each packed pair; CFL maximum of |u|_1
-    float m = 0.f;
-    C c[3][E];
+        for (int i = 0; i < E; ++i) {
+            const C w = mk<T>(v[i].x, -v[i].y);
+            if (f < 3) {
+                uu[f][i] = w;
+            } else if (f == 3) {  // omega_x: c_y += u_z w, c_z = -u_y w
+                c[0][i] = mk<T>(0, 0);
+                c[1][i] = mk<T>(uu[2][i].x * w.x, uu[2][i].y * w.y);
+                c[2][i] = mk<T>(-uu[1][i].x * w.x, -uu[1][i].y * w.y);
+            } else if (f == 4) {  // omega_y: c_x -= u_z w, c_z += u_x w
+                c[0][i] = mk<T>(c[0][i].x - uu[2][i].x * w.x, c[0][i].y - uu[2][i].y * w.y);
+                c[2][i] = mk<T>(c[2][i].x + uu[0][i].x * w.x, c[2][i].y + uu[0][i].y * w.y);
+            } else {  // omega_z: c_x += u_y w, c_y -= u_x w
+                c[0][i] = mk<T>(c[0][i].x + uu[1][i].x * w.x, c[0][i].y + uu[1][i].y * w.y);
+                c[1][i] = mk<T>(c[1][i].x - uu[0][i].x * w.x, c[1][i].y - uu[0][i].y * w.y);
+            }
+        }
+        if (f == 2 && umax) {  // CFL maximum of |u|_1 over the line's samples
+            float m = 0.f;
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const C ux = r[0][i], uy = r[1][i], uz = r[2][i], wx = r[3][i], wy = r[4][i], wz = r[5][i];
-        c[0][i] = mk<T>(uy.x * wz.x - uz.x * wy.x, uy.y * wz.y - uz.y * wy.y);
-        c[1][i] = mk<T>(uz.x * wx.x - ux.x * wz.x, uz.y * wx.y - ux.y * wz.y);
-        c[2][i] = mk<T>(ux.x * wy.x - uy.x * wx.x, ux.y * wy.y - uy.y * wx.y);
-        const float s0 = (float)(fabs(ux.x) + fabs(uy.x) + fabs(uz.x));
-        const float s1 = (float)(fabs(ux.y) + fabs(uy.y) + fabs(uz.y));
-        m = fmaxf(m, fmaxf(s0, s1));
-    }
-    if (umax) {
-        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-        if ((tid & 63) == 0 && valid) atomicMax(umax, __float_as_uint(m));
+            for (int i = 0; i < E; ++i) {
+                const float s0 = (float)(fabs(uu[0][i].x) + fabs(uu[1][i].x) + fabs(uu[2][i].x));
+                const float s1 = (float)(fabs(uu[0][i].y) + fabs(uu[1][i].y) + fabs(uu[2][i].y));
+                m = fmaxf(m, fmaxf(s0, s1));
+            }
+            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+            if ((tid & 63) == 0 && valid) atomicMax(umax, __float_as_uint(m));
+        }
     }
     // forward r2c of the three products (unscaled; P5 applies 1/N^3)
 #pragma unroll
@@ -193,9 +207,8 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = c[f][i];
         line_fft<T, L, E, 1, 2>(v, d, jt, tw);
-#pragma unroll
-        for (int i = 0; i < E; ++i) d[lds_at<1>(jt + i * TPL)] = v[i];
-        __syncthreads();
+        C zm[E];
+        mirror<T, L, E>(v, zm, jt);
         if (valid) {
             C *o = w6 + f * FS + l * NZH;
 #pragma unroll
@@ -203,14 +216,13 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
                 const int k = jt + i * TPL;
                 if (k < KZC) {
                     const C zk = v[i];
-                    const C zm = cconj(d[lds_at<1>((L - k) % L)]);
-                    const C a = cadd(zk, zm);
-                    const C b = cmul(tw[k], csub(zk, zm));
+                    const C zc = cconj(zm[i]);
+                    const C a = cadd(zk, zc);
+                    const C b = cmul(tw[k], csub(zk, zc));
                     o[k] = mk<T>((T)0.5 * (a.x + b.y), (T)0.5 * (a.y - b.x));
                 }
             }
         }
-        __syncthreads();
     }
 }
 
