@@ -195,7 +195,7 @@ def traffic_from_profile(kernel_name):
                 rec[parts[1]] = float(parts[2])
     if rec.get("digest") != digest:
         return None
-    return rec.get(kernel_name)
+    return rec.get(kernel_name.replace(" ", ""))
 
 
 def cpu_baseline(n=512):
