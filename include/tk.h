@@ -69,6 +69,7 @@ tk_status tk_sum_squares(const void *x, long n, tk_dtype dt, double *out, void *
 /* Flags for fft3d_plan_create. */
 #define TK_FFT_TIMING 0x1u    /* record per-pass HIP events (fft3d_pass_times) */
 #define TK_FFT_NO_TUNE 0x2u   /* ignore the autotuner cache, use default tiles */
+#define TK_FFT_C2R_Y_FIRST 0x4u /* c2r: inverse Y (out of place) before X (in place); same result */
 
 /* Create a plan for `batch` fields of nx*ny*nz points in dtype dt.  Allocates twiddle
  * tables (a few KB) on the current device.  Sizes must be supported (see above);

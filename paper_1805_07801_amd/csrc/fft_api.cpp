@@ -208,9 +208,16 @@ extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out
     const FftAxes &ax = p->ax;
     hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
-    TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s));
-    if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
-    TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
+    if (p->flags & TK_FFT_C2R_Y_FIRST) {
+        // the X and Y inverses commute: the one out-of-place pass is then the Y pass
+        TK_TRY(fft_y_pass(ax, cplx_in, p->ws, p->batch, 1, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_x_pass(ax, p->ws, p->ws, p->batch, 1, 1.0, s));
+    } else {
+        TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
+    }
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
     TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s));
     if (ev) {

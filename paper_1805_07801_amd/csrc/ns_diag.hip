@@ -67,16 +67,20 @@ __global__ __launch_bounds__(DB) void k_diag(const V2<T> *__restrict__ u, int N,
     for (int i = threadIdx.x; i < nshell; i += DB) p[4 + i] = hist[i];
 }
 
-// Column-wise sum (max for entries 2 and 3) of nb partial rows, in block order.
-__global__ void k_diag_final(const double *__restrict__ part, int nb, int stride, int nvals, double *__restrict__ out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nvals; i += gridDim.x * blockDim.x) {
-        double acc = 0;
-        for (int b = 0; b < nb; ++b) {
-            const double v = part[(long)b * stride + i];
-            acc = (i == 2 || i == 3) ? fmax(acc, v) : acc + v;
-        }
-        out[i] = acc;
+// Column-wise sum (max for entries 2 and 3) of nb partial rows: one workgroup per column,
+// a fixed strided split over threads and a fixed tree (deterministic).
+__global__ __launch_bounds__(DB) void k_diag_final(const double *__restrict__ part, int nb, int stride,
+                                                   double *__restrict__ out) {
+    __shared__ double sh[DB / 64];
+    const int i = blockIdx.x;
+    const bool mx = (i == 2 || i == 3);
+    double acc = 0;
+    for (int b = threadIdx.x; b < nb; b += DB) {
+        const double v = part[(long)b * stride + i];
+        acc = mx ? fmax(acc, v) : acc + v;
     }
+    acc = mx ? block_max(acc, sh) : block_sum(acc, sh);
+    if (threadIdx.x == 0) out[i] = acc;
 }
 
 tk_status ns_diag_run(const void *u, int N, tk_dtype dt, int nshell, double *dscratch, double *hout,
@@ -91,7 +95,7 @@ tk_status ns_diag_run(const void *u, int N, tk_dtype dt, int nshell, double *dsc
     else
         hipLaunchKernelGGL(k_diag<double>, dim3(nb), dim3(DB), shm, s, (const double2 *)u, N, nshell, part, stride);
     TK_TRY(launch_check("diagnostics"));
-    hipLaunchKernelGGL(k_diag_final, dim3(cdiv(stride, 256)), dim3(256), 0, s, part, nb, stride, stride, out);
+    hipLaunchKernelGGL(k_diag_final, dim3(stride), dim3(DB), 0, s, part, nb, stride, out);
     TK_TRY(launch_check("diagnostics final"));
     TK_HIP_CHECK(hipMemcpyAsync(hout, out, sizeof(double) * stride, hipMemcpyDeviceToHost, s));
     TK_HIP_CHECK(hipStreamSynchronize(s));
