@@ -184,6 +184,20 @@ tk_status ns_last_dt(tk_ns_t ns, double *dt);
 
 tk_status ns_destroy(tk_ns_t ns);
 
+/* Energy transfer (the paper lists energy flux and shell-to-shell transfer among the
+ * solver's diagnostics).  T[s] = sum_{k in shell s} w Re[u^*(k) . N(k)] for the first
+ * nshell integer shells (N the nonlinear term of ns_rhs), FP64; the energy flux out of
+ * the sphere s0 is -sum_{s <= s0} T[s].  Uses the solver's workspace.  Synchronises. */
+tk_status ns_energy_transfer(tk_ns_t ns, const void *uhat, double *T, int nshell, void *stream);
+
+/* Giver/receiver shell-to-shell transfer between bands of integer shells
+ * (band_of_shell[s] in [0, nbands) or -1, host array of nshell ints):
+ *   Tnm[n * nbands + m] = - sum_{k in band n} w Re[u^*(k) . F((u . grad) u^(m))(k)],
+ * u^(m) = u restricted to band m (energy given by band m to band n).  Allocates about
+ * 25 real / spectral fields of workspace for the call.  Synchronises. */
+tk_status ns_shell_to_shell(tk_ns_t ns, const void *uhat, const int *band_of_shell, int nshell, int nbands,
+                            double *Tnm, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * Ensembles: `count` independent FP32 solves of mixed grid sizes n[i] in {16, 24, 32,
  * 48, 64, 96, 128} with viscosities nu[i], advanced together by IF-RK2.  Every pass of

@@ -63,6 +63,8 @@ def _declare(L):
         "ns_init_random": ([vp, vp, vp, d, vp], i),
         "ns_last_dt": ([vp, P(d)], i),
         "ns_destroy": ([vp], i),
+        "ns_energy_transfer": ([vp, vp, P(d), i, vp], i),
+        "ns_shell_to_shell": ([vp, vp, P(i), i, i, P(d), vp], i),
         "ns_batch_create": ([P(vp), i, P(i), P(d), i, d, u], i),
         "ns_batch_step": ([vp, P(vp), d, i, P(d), vp], i),
         "ns_batch_init_random": ([vp, i, vp, vp, d, vp], i),
@@ -319,6 +321,23 @@ class NS:
                                    ctypes.byref(md), _stream(stream)))
         return {"energy": e.value, "dissipation": eps.value, "max_div": md.value,
                 "spectrum": [spec[i] for i in range(nshell)]}
+
+    def energy_transfer(self, u, nshell=None, stream=None):
+        """T(s) per integer shell (FP64); flux = -cumsum(T)."""
+        self._check_state(u)
+        nshell = num_shells(self.n) if nshell is None else nshell
+        T = (ctypes.c_double * nshell)()
+        check(lib().ns_energy_transfer(self.h, _ptr(u), T, nshell, _stream(stream)))
+        return [T[i] for i in range(nshell)]
+
+    def shell_to_shell(self, u, band_of_shell, nbands, stream=None):
+        """[receiver][giver] transfer matrix between bands of integer shells."""
+        self._check_state(u)
+        ns_ = len(band_of_shell)
+        b = (ctypes.c_int * ns_)(*[int(v) for v in band_of_shell])
+        T = (ctypes.c_double * (nbands * nbands))()
+        check(lib().ns_shell_to_shell(self.h, _ptr(u), b, ns_, nbands, T, _stream(stream)))
+        return [[T[r * nbands + m] for m in range(nbands)] for r in range(nbands)]
 
     def init_random(self, noise, energy=1.0, out=None, stream=None):
         """Random solenoidal state from real noise [3][n][n][n] (see ns_init_random)."""
