@@ -43,6 +43,7 @@ typedef enum { TK_F32 = 0, TK_F64 = 1 } tk_dtype;
 typedef struct tk_fft3d_s *tk_fft3d_t;
 typedef struct tk_ns_s *tk_ns_t;
 typedef struct tk_nsb_s *tk_nsb_t;
+typedef struct tk_rbc_s *tk_rbc_t;
 
 /* Thread-local text describing the last non-OK status of this thread ("" if none). */
 const char *tk_last_error(void);
@@ -197,6 +198,36 @@ tk_status ns_energy_transfer(tk_ns_t ns, const void *uhat, double *T, int nshell
  * 25 real / spectral fields of workspace for the call.  Synchronises. */
 tk_status ns_shell_to_shell(tk_ns_t ns, const void *uhat, const int *band_of_shell, int nshell, int nbands,
                             double *Tnm, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Rayleigh-Benard (Boussinesq) convection, periodic FFF basis: paper, Section "Spectral
+ * Solver", eq:u_Usmall_Plarge and eq:T_Usmall_Plarge (viscosity sqrt(Pr/Ra), thermal
+ * diffusivity 1/sqrt(Ra Pr), buoyancy theta z, source u_z in the temperature equation), in
+ * a periodic box of side `box` (the paper's unit cube: box = 1; wavenumbers 2 pi k / box).
+ * State [4][n][n][n/2+1]: u_x, u_y, u_z, theta; 2/3-masked, u solenoidal.  One right-hand
+ * side = 7 inverse + 6 forward transforms (13, as the paper counts); IF-RK2 steps.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    int n;
+    tk_dtype dtype;
+    double Ra, Pr; /* Rayleigh and Prandtl numbers */
+    double box;    /* box side (> 0) */
+    double cfl;    /* > 0: h = cfl (box / n) / max(|ux|+|uy|+|uz|); else the dt given to rbc_step */
+    unsigned flags;
+} rbc_config;
+
+tk_status rbc_create(tk_rbc_t *rbc, const rbc_config *cfg);
+/* (N_u, N_theta) = (P M [F(u x omega) + theta z], M [-i a k . F(u theta) + u_z]), diffusion
+ * excluded, a = 2 pi / box; rhs_out has the state's layout. */
+tk_status rbc_rhs(tk_rbc_t rbc, const void *state, void *rhs_out, void *stream);
+/* Advance in place by nsteps IF-RK2 steps (one HIP-graph launch each); synchronises. */
+tk_status rbc_step(tk_rbc_t rbc, void *state, double dt, int nsteps, double *t_inout, void *stream);
+/* FP64: kinetic energy, thermal variance 1/2 <theta^2>, <u_z theta> and the Nusselt number
+ * 1 + sqrt(Ra Pr) <u_z theta> (any pointer may be NULL).  Synchronises. */
+tk_status rbc_diagnostics(tk_rbc_t rbc, const void *state, double *kinetic, double *thermal, double *uz_theta,
+                          double *nusselt, void *stream);
+tk_status rbc_last_dt(tk_rbc_t rbc, double *dt);
+tk_status rbc_destroy(tk_rbc_t rbc);
 
 /* ------------------------------------------------------------------------------------
  * Ensembles: `count` independent FP32 solves of mixed grid sizes n[i] in {16, 24, 32,

@@ -31,6 +31,11 @@ class TkAdam(ctypes.Structure):
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("step", ctypes.c_int)]
 
 
+class RbcConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("Ra", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("box", ctypes.c_double), ("cfl", ctypes.c_double), ("flags", ctypes.c_uint)]
+
+
 class NsConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("scheme", ctypes.c_int), ("flags", ctypes.c_uint)]
@@ -64,6 +69,12 @@ def _declare(L):
         "ns_last_dt": ([vp, P(d)], i),
         "ns_destroy": ([vp], i),
         "ns_energy_transfer": ([vp, vp, P(d), i, vp], i),
+        "rbc_create": ([P(vp), P(RbcConfig)], i),
+        "rbc_rhs": ([vp, vp, vp, vp], i),
+        "rbc_step": ([vp, vp, d, i, P(d), vp], i),
+        "rbc_diagnostics": ([vp, vp, P(d), P(d), P(d), P(d), vp], i),
+        "rbc_last_dt": ([vp, P(d)], i),
+        "rbc_destroy": ([vp], i),
         "ns_shell_to_shell": ([vp, vp, P(i), i, i, P(d), vp], i),
         "ns_batch_create": ([P(vp), i, P(i), P(d), i, d, u], i),
         "ns_batch_step": ([vp, P(vp), d, i, P(d), vp], i),
@@ -497,3 +508,53 @@ def les_step(ns, closure, u, dt, nsteps=1, t=0.0):
     check(lib().les_step(ns.h, ctypes.byref(d) if d is not None else None, _ptr(u), float(dt), int(nsteps),
                          ctypes.byref(tt), ctypes.byref(fb), _stream()))
     return tt.value, fb.value
+
+
+class RBC:
+    """Boussinesq convection in the periodic FFF basis; state [4][n][n][n/2+1] (u, theta)."""
+
+    def __init__(self, n, Ra, Pr=1.0, box=1.0, dtype=None, cfl=0.0):
+        import torch
+        dtype = dtype or torch.float32
+        self.n = n
+        self.dtype = dtype
+        self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
+        cfg = RbcConfig(n, _dtype_code(dtype), float(Ra), float(Pr), float(box), float(cfl), 0)
+        h = ctypes.c_void_p()
+        check(lib().rbc_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self.h = h
+
+    def _check(self, t):
+        n = self.n
+        if t.dtype != self.cdtype or not t.is_cuda or not t.is_contiguous() or t.numel() != 4 * n * n * (n // 2 + 1):
+            raise TkError(TK_EINVAL, "state must be a contiguous %s GPU tensor [4][n][n][n/2+1]" % self.cdtype)
+
+    def rhs(self, s4, out=None, stream=None):
+        import torch
+        self._check(s4)
+        out = torch.empty_like(s4) if out is None else out
+        check(lib().rbc_rhs(self.h, _ptr(s4), _ptr(out), _stream(stream)))
+        return out
+
+    def step(self, s4, dt, nsteps=1, t=0.0, stream=None):
+        self._check(s4)
+        tt = ctypes.c_double(t)
+        check(lib().rbc_step(self.h, _ptr(s4), float(dt), int(nsteps), ctypes.byref(tt), _stream(stream)))
+        return tt.value
+
+    def diagnostics(self, s4, stream=None):
+        self._check(s4)
+        v = [ctypes.c_double() for _ in range(4)]
+        check(lib().rbc_diagnostics(self.h, _ptr(s4), *[ctypes.byref(x) for x in v], _stream(stream)))
+        return {"kinetic": v[0].value, "thermal": v[1].value, "uz_theta": v[2].value, "nusselt": v[3].value}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            lib().rbc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -58,9 +58,11 @@ __device__ __forceinline__ long kept_col(long cc, int N, int K, int KZC, int NZH
 }
 
 // ---- P1: X-inverse with curl on load -------------------------------------------------------------
-template <typename T, int L, int E, int W>
+// RBC = true: a fourth input field (temperature) is passed through as a seventh output.
+// ka scales the wavenumbers of the curl (2 pi / box side).
+template <typename T, int L, int E, int W, bool RBC = false>
 __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int KZC,
-                                           long tile, V2<T> *lds, const V2<T> *tw) {
+                                           long tile, V2<T> *lds, const V2<T> *tw, T ka = (T)1) {
     using C = V2<T>;
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
@@ -76,8 +78,9 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    const int kyd = ky, kzd = (2 * kz == N) ? 0 : kz;
-    C a0[E], a1[E], a2[E];
+    const T kyd = ka * (T)ky, kzd = ka * (T)((2 * kz == N) ? 0 : kz);
+    constexpr int NOUT = RBC ? 7 : 6;
+    C a0[E], a1[E], a2[E], a3[RBC ? E : 1];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int r = jt + i * TPL;
@@ -86,23 +89,25 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
         a0[i] = ld ? u[o] : mk<T>(0, 0);
         a1[i] = ld ? u[FS + o] : mk<T>(0, 0);
         a2[i] = ld ? u[2 * FS + o] : mk<T>(0, 0);
+        if constexpr (RBC) a3[i] = ld ? u[3 * FS + o] : mk<T>(0, 0);
     }
 #pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < NOUT; ++f) {
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const int kx = deriv_k(jt + i * TPL, N);
+            const T kx = ka * (T)deriv_k(jt + i * TPL, N);
             C x;
             if (f == 0) x = a0[i];
             else if (f == 1) x = a1[i];
             else if (f == 2) x = a2[i];
+            else if (RBC && f == 6) x = a3[RBC ? i : 0];
             else {
                 // omega = i k x u
                 C b;
-                if (f == 3) b = csub(cscale(a2[i], (T)kyd), cscale(a1[i], (T)kzd));
-                else if (f == 4) b = csub(cscale(a0[i], (T)kzd), cscale(a2[i], (T)kx));
-                else b = csub(cscale(a1[i], (T)kx), cscale(a0[i], (T)kyd));
+                if (f == 3) b = csub(cscale(a2[i], kyd), cscale(a1[i], kzd));
+                else if (f == 4) b = csub(cscale(a0[i], kzd), cscale(a2[i], kx));
+                else b = csub(cscale(a1[i], kx), cscale(a0[i], kyd));
                 x = cmul_pi(b);
             }
             v[i] = cconj(x);  // inverse transform as conj(DFT(conj .))
@@ -116,22 +121,23 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
     }
 }
 
-template <typename T, int L, int E, int W>
+template <typename T, int L, int E, int W, bool RBC = false>
 __global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
-                                                       int KZC, const V2<T> *__restrict__ twg) {
+                                                       int KZC, const V2<T> *__restrict__ twg, T ka) {
     using C = V2<T>;
     __shared__ C lds[L * (W + 1)];
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
     __syncthreads();
-    ns_p1_tile<T, L, E, W>(u, w6, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw);
+    ns_p1_tile<T, L, E, W, RBC>(u, w6, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, ka);
 }
 
 // ---- P3: fused Z pass ------------------------------------------------------------------------------
 // Lines l = x * N + y of the 6 fields in w6 (kz < KZC nonzero); outputs c = u x omega
 // transformed back, kz < KZC, into fields 0..2 of w6 (in place: each workgroup reads all
 // six fields of its lines before it writes).  lds: LPW lines of lds_line_len<L>().
-template <typename T, int L, int E, int LPW>
+// RBC = true: a seventh input (temperature theta) gives three more outputs q = u theta.
+template <typename T, int L, int E, int LPW, bool RBC = false>
 __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long tile, V2<T> *lds, const V2<T> *tw,
                                            unsigned *umax) {
     using C = V2<T>;
@@ -148,9 +154,11 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     C *d = lds + ln * LL;
     // real-space samples, packed pairs (x[2n], x[2n+1]) at n = jt + i TPL: u is kept, the
     // three vorticity components are folded into c = u x omega as they arrive
-    C uu[3][E], c[3][E];
+    constexpr int NIN = RBC ? 7 : 6;
+    constexpr int NOUT = RBC ? 6 : 3;
+    C uu[3][E], c[NOUT][E];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < NIN; ++f) {
         const C *s = w6 + f * FS + (valid ? l : 0) * NZH;
         C v[E], xm[E];
 #pragma unroll
@@ -183,9 +191,12 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             } else if (f == 4) {  // omega_y: c_x -= u_z w, c_z += u_x w
                 c[0][i] = mk<T>(c[0][i].x - uu[2][i].x * w.x, c[0][i].y - uu[2][i].y * w.y);
                 c[2][i] = mk<T>(c[2][i].x + uu[0][i].x * w.x, c[2][i].y + uu[0][i].y * w.y);
-            } else {  // omega_z: c_x += u_y w, c_y -= u_x w
+            } else if (f == 5) {  // omega_z: c_x += u_y w, c_y -= u_x w
                 c[0][i] = mk<T>(c[0][i].x + uu[1][i].x * w.x, c[0][i].y + uu[1][i].y * w.y);
                 c[1][i] = mk<T>(c[1][i].x - uu[0][i].x * w.x, c[1][i].y - uu[0][i].y * w.y);
+            } else if constexpr (RBC) {  // theta: q_j = u_j theta
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) c[3 + jj][i] = mk<T>(uu[jj][i].x * w.x, uu[jj][i].y * w.y);
             }
         }
         if (f == 2 && umax) {  // CFL maximum of |u|_1 over the line's samples
@@ -200,9 +211,9 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             if ((tid & 63) == 0 && valid) atomicMax(umax, __float_as_uint(m));
         }
     }
-    // forward r2c of the three products (unscaled; P5 applies 1/N^3)
+    // forward r2c of the products (unscaled; P5 applies 1/N^3)
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < NOUT; ++f) {
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = c[f][i];
@@ -226,7 +237,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     }
 }
 
-template <typename T, int L, int E, int LPW>
+template <typename T, int L, int E, int LPW, bool RBC = false>
 __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, int KZC,
                                                          const V2<T> *__restrict__ twg, unsigned *umax) {
     using C = V2<T>;
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, 
     __shared__ C tw[2 * L];
     load_twiddles<T>(tw, twg, 2 * L, threadIdx.x, LPW * (L / E));
     __syncthreads();
-    ns_p3_tile<T, L, E, LPW>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, umax);
+    ns_p3_tile<T, L, E, LPW, RBC>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, umax);
 }
 
 // ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
@@ -368,6 +379,118 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ 
                            tw);
 }
 
+// ---- P5 of the Boussinesq (RBC) right-hand side ----------------------------------------------------
+// Fields in: c = u x omega (0..2) and q = u theta (3..5) after P4; stage input uin = (u, theta).
+//   N_u = P M [c^ + theta^ z],   N_theta = M [-i a k . q^ + u_z^]
+// then the IF-RK2 combine over 4 fields with exp(-nu_a |k|^2 h) for u and exp(-kappa_a |k|^2 h)
+// for theta (nu_a, kappa_a already include a^2).  Modes: NS_RHS, RK2_S1, RK2_S2.
+template <typename T, int L, int E, int W>
+__device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const V2<T> *__restrict__ uin, V2<T> *u,
+                                            V2<T> *aux, V2<T> *ust, V2<T> *out, const NsState *__restrict__ st,
+                                            double nu_a, double kap_a, T ka, int mode, int K, int KZC, long tile,
+                                            V2<T> *lds, const V2<T> *tw) {
+    using C = V2<T>;
+    constexpr int N = L;
+    constexpr int NZH = N / 2 + 1;
+    constexpr int TPL = L / E;
+    constexpr int ES = W + 1;
+    constexpr long FS = (long)N * N * NZH;
+    constexpr long RS = (long)N * NZH;
+    const int tid = threadIdx.x;
+    const int col = tid % W;
+    const int jt = tid / W;
+    const long ncols = (long)(2 * K + 1) * KZC;
+    const long cc = tile * W + col;
+    const bool valid = cc < ncols;
+    int ky = 0, kz = 0;
+    const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    C cf[3][E], nt[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) nt[i] = mk<T>(0, 0);
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = valid ? c6[f * FS + (long)(jt + i * TPL) * RS + j] : mk<T>(0, 0);
+        line_fft<T, L, E, ES>(v, lds + col, jt, tw);
+        if (f < 3) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                if (f == 0) cf[0][i] = v[i];
+                else if (f == 1) cf[1][i] = v[i];
+                else cf[2][i] = v[i];
+            }
+        } else {
+            // -i a k_f q^_f accumulated: (-i) (a k) (x + i y) = a k (y - i x)
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const T kf = ka * (T)(f == 3 ? deriv_k(jt + i * TPL, N) : (f == 4 ? ky : ((2 * kz == N) ? 0 : kz)));
+                nt[i].x += kf * v[i].y;
+                nt[i].y -= kf * v[i].x;
+            }
+        }
+    }
+    if (valid) {
+        const T scale = (T)(1.0 / ((double)N * N * N));
+        const double h = st->h;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int r = jt + i * TPL;
+            if (!row_kept(r, L, K)) continue;
+            const int kx = wave_k(r, N);
+            const long o = (long)r * RS + j;
+            const C th = uin[3 * FS + o];
+            C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cadd(cscale(cf[2][i], scale), th);
+            const T k2 = (T)(kx * kx + ky * ky + kz * kz);
+            if (k2 > 0) {
+                const T ik2 = (T)1 / k2;
+                const C kd = cadd(cadd(cscale(n0, (T)kx), cscale(n1, (T)ky)), cscale(n2, (T)kz));
+                n0 = csub(n0, cscale(kd, (T)kx * ik2));
+                n1 = csub(n1, cscale(kd, (T)ky * ik2));
+                n2 = csub(n2, cscale(kd, (T)kz * ik2));
+            } else {
+                n0 = n1 = n2 = mk<T>(0, 0);
+            }
+            const C n3 = cadd(cscale(nt[i], scale), uin[2 * FS + o]);
+            const C nn[4] = {n0, n1, n2, n3};
+            if (mode == NS_RHS) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) out[f * FS + o] = nn[f];
+                continue;
+            }
+            const T eu = (T)exp(-nu_a * (double)k2 * h);
+            const T et = (T)exp(-kap_a * (double)k2 * h);
+            const T th_ = (T)h;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const long q = f * FS + o;
+                const T e = f < 3 ? eu : et;
+                const C uu = u[q];
+                if (mode == RK2_S1) {
+                    aux[q] = nn[f];
+                    ust[q] = cscale(cadd(uu, cscale(nn[f], th_)), e);
+                } else {
+                    u[q] = cadd(cscale(uu, e), cscale(cadd(cscale(aux[q], e), nn[f]), (T)0.5 * th_));
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_rbc_p5(const V2<T> *__restrict__ c6, const V2<T> *__restrict__ uin,
+                                                        V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
+                                                        const NsState *__restrict__ st, double nu_a, double kap_a,
+                                                        T ka, int mode, int K, int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    __shared__ C lds[L * (W + 1)];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
+    __syncthreads();
+    rbc_p5_tile<T, L, E, W>(c6, uin, u, aux, ust, out, st, nu_a, kap_a, ka, mode, K, KZC,
+                            xcd_tile(blockIdx.x, gridDim.x), lds, tw);
+}
+
 // ---- small kernels --------------------------------------------------------------------------------
 // CFL step size from the maximum P3 recorded (or the fixed step); advances t; clears umax.
 static __global__ void k_ns_set_h(NsState *st) {
@@ -414,6 +537,11 @@ struct NsKernels {
     int N;
     tk_dtype dt;
     void (*p1)(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s);
+    // Boussinesq variants: P1 with temperature (4 -> 7 fields), P3 (7 -> 6), P5 (6 + state of 4)
+    void (*p1r)(const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s);
+    void (*p3r)(void *w7, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s);
+    void (*p5r)(const void *c6, const void *uin, void *u, void *aux, void *ust, void *out, const NsState *st,
+                double nu_a, double kap_a, double ka, int mode, int K, int KZC, const void *tw, hipStream_t s);
     void (*p3)(void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s);
     void (*p5)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
 };
@@ -431,7 +559,23 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     k.p1 = [](const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
         const long ncols = (long)(2 * K + 1) * KZC;
         hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
-                           (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw);
+                           (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
+    };
+    k.p1r = [](const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s) {
+        const long ncols = (long)(2 * K + 1) * KZC;
+        hipLaunchKernelGGL((k_ns_p1<T, N, E, W, true>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+                           (const V2<T> *)u, (V2<T> *)w7, K, KZC, (const V2<T> *)tw, (T)ka);
+    };
+    k.p3r = [](void *w7, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s) {
+        hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW, true>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
+                           (V2<T> *)w7, nlines, KZC, (const V2<T> *)tw, umax);
+    };
+    k.p5r = [](const void *c6, const void *uin, void *u, void *aux, void *ust, void *out, const NsState *st,
+               double nu_a, double kap_a, double ka, int mode, int K, int KZC, const void *tw, hipStream_t s) {
+        const long ncols = (long)(2 * K + 1) * KZC;
+        hipLaunchKernelGGL((k_rbc_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+                           (const V2<T> *)c6, (const V2<T> *)uin, (V2<T> *)u, (V2<T> *)aux, (V2<T> *)ust,
+                           (V2<T> *)out, st, nu_a, kap_a, (T)ka, mode, K, KZC, (const V2<T> *)tw);
     };
     k.p3 = [](void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s) {
         hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
