@@ -140,3 +140,89 @@ def idft_at(F, nz, xs):
         g = ey @ g                                     # [nzh]
         out.append(np.sum(w * np.real(g * ez)))
     return np.array(out)
+
+
+# ---- sine / cosine bases (free-slip walls) -------------------------------------------------------
+# Paper, Section "Fast Fourier Transform": besides exp(iks) an axis may use the sine basis
+# 2 sin(ks) or the cosine basis 2 cos(ks) (the SFF / SSF bases).  Readings: on such an axis
+# the N grid points are x_j = pi (j + 1/2) / N (the half-period [0, pi]); the inverse is
+#   cosine: f(x) = F_0 + sum_{k=1}^{N-1} 2 F_k cos(k x)
+#   sine:   f(x) = sum_{k=1}^{N-1} 2 F_k sin(k x) + F_N sin(N x)
+# and the forward transform, its inverse, is F_k = (1/N) sum_j f(x_j) cos(k x_j) (cosine,
+# k = 0..N-1) or (1/N) sum_j f(x_j) sin(k x_j) (sine, k = 1..N, stored at index k-1).
+FOURIER, SINE, COSINE = 0, 1, 2
+
+
+def _r2r_matrix(n, basis, inverse):
+    j = np.arange(n)
+    x = np.pi * (j + 0.5) / n
+    if basis == COSINE:
+        k = np.arange(n)
+        M = np.cos(np.outer(k, x))                    # [k][j]
+        if inverse:
+            c = np.full(n, 2.0)
+            c[0] = 1.0
+            return (M * c[:, None]).T                 # f_j = sum_k c_k F_k cos
+        return M / n
+    k = np.arange(1, n + 1)
+    M = np.sin(np.outer(k, x))
+    if inverse:
+        c = np.full(n, 2.0)
+        c[-1] = 1.0
+        return (M * c[:, None]).T
+    return M / n
+
+
+def _apply_axis(a, M, axis):
+    return np.moveaxis(np.tensordot(M, np.moveaxis(a, axis, 0), axes=(1, 0)), 0, axis)
+
+
+def rfft3_basis(f, bx=FOURIER, by=FOURIER):
+    """Forward 3D transform with basis bx along x and by along y (Fourier along z):
+    [nx][ny][nz] real -> [nx][ny][nz/2+1] complex, 1/N normalisation on every axis."""
+    f = np.asarray(f, dtype=np.float64)
+    nx, ny, nz = f.shape
+    if bx == FOURIER and by == FOURIER:
+        return rfft3(f)
+    # z first, then y, then x, each axis by its own definition
+    out = np.zeros((nx, ny, nz // 2 + 1), complex)
+    for a in range(nx):
+        for b in range(ny):
+            line = fft1d(f[a, b].astype(np.complex128), -1)[: nz // 2 + 1] / nz
+            out[a, b] = line
+    if by == FOURIER:
+        out = np.stack([np.stack([fft1d(out[a, :, c], -1) / ny for c in range(nz // 2 + 1)], axis=1)
+                        for a in range(nx)])
+    else:
+        out = _apply_axis(out, _r2r_matrix(ny, by, False), 1)
+    if bx == FOURIER:
+        out = np.stack([np.stack([fft1d(out[:, b, c], -1) / nx for c in range(nz // 2 + 1)], axis=1)
+                        for b in range(ny)], axis=1)
+    else:
+        out = _apply_axis(out, _r2r_matrix(nx, bx, False), 0)
+    return out
+
+
+def irfft3_basis(F, nz, bx=FOURIER, by=FOURIER):
+    """Inverse of rfft3_basis (unscaled on Fourier axes, the basis sums on sine/cosine axes)."""
+    F = np.asarray(F, dtype=np.complex128)
+    nx, ny, nzh = F.shape
+    g = F.copy()
+    if bx == FOURIER:
+        g = np.stack([np.stack([fft1d(g[:, b, c], +1) for c in range(nzh)], axis=1) for b in range(ny)], axis=1)
+    else:
+        g = _apply_axis(g, _r2r_matrix(nx, bx, True), 0)
+    if by == FOURIER:
+        g = np.stack([np.stack([fft1d(g[a, :, c], +1) for c in range(nzh)], axis=1) for a in range(nx)])
+    else:
+        g = _apply_axis(g, _r2r_matrix(ny, by, True), 1)
+    out = np.empty((nx, ny, nz))
+    for a in range(nx):
+        for b in range(ny):
+            line = np.zeros(nz, complex)
+            line[0] = g[a, b, 0].real
+            line[nz // 2] = g[a, b, nz // 2].real
+            line[1:nz // 2] = g[a, b, 1:nz // 2]
+            line[nz // 2 + 1:] = np.conj(g[a, b, 1:nz // 2][::-1])
+            out[a, b] = fft1d(line, +1).real
+    return out
