@@ -78,6 +78,20 @@ tk_status tk_sum_squares(const void *x, long n, tk_dtype dt, double *out, void *
 tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
                             unsigned flags);
 
+/* Bases of an axis (paper, Section "Fast Fourier Transform": exp(iks), 2 sin(ks), 2 cos(ks);
+ * the SFF / SSF combinations for free-slip walls). */
+#define TK_FOURIER 0
+#define TK_SINE 1
+#define TK_COSINE 2
+
+/* As fft3d_plan_create, with the sine or cosine basis along x and/or y (z stays Fourier).
+ * On a sine/cosine axis of N points the grid is x_j = pi (j + 1/2) / N; the forward
+ * transform is F_k = (1/N) sum_j f_j cos(k x_j) (k = 0..N-1) or (1/N) sum_j f_j sin(k x_j)
+ * (k = 1..N, stored at index k - 1), and the inverse f = F_0 + sum_{k>0} 2 F_k cos(k x) or
+ * f = sum_{k<N} 2 F_k sin(k x) + F_N sin(N x).  Layouts as for the Fourier basis. */
+tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt, int basis_x,
+                                  int basis_y, unsigned flags);
+
 /* Bytes of device workspace fft3d_c2r needs (one spectral field per batch member). */
 tk_status fft3d_workspace_size(tk_fft3d_t plan, size_t *bytes);
 

@@ -49,6 +49,7 @@ def _declare(L):
         "tk_version": ([], i),
         "tk_sum_squares": ([vp, ctypes.c_long, i, P(d), vp], i),
         "fft3d_plan_create": ([P(vp), i, i, i, i, i, u], i),
+        "fft3d_plan_create_basis": ([P(vp), i, i, i, i, i, i, i, u], i),
         "fft3d_workspace_size": ([vp, P(sz)], i),
         "fft3d_set_workspace": ([vp, vp], i),
         "fft3d_r2c": ([vp, vp, vp, vp], i),
@@ -198,7 +199,8 @@ def tune_load(path):
 class FFT3D:
     """Plan for batched 3D r2c / c2r transforms of [batch][nx][ny][nz] real fields."""
 
-    def __init__(self, nx, ny=None, nz=None, batch=1, dtype=None, flags=0):
+    def __init__(self, nx, ny=None, nz=None, batch=1, dtype=None, flags=0, basis_x=0, basis_y=0):
+        """basis_x / basis_y: 0 Fourier, 1 sine, 2 cosine (z is Fourier)."""
         import torch
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
@@ -208,7 +210,11 @@ class FFT3D:
         self.dtype = dtype
         self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
         h = ctypes.c_void_p()
-        check(lib().fft3d_plan_create(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), flags))
+        if basis_x or basis_y:
+            check(lib().fft3d_plan_create_basis(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), basis_x,
+                                                basis_y, flags))
+        else:
+            check(lib().fft3d_plan_create(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), flags))
         self.h = h
 
     def _check_real(self, t):

@@ -50,8 +50,20 @@ tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long 
     return launch_check("strided pass");
 }
 
+static tk_status r2r_pass(const R2RKernel *k, int basis, const void *src, void *dst, long ncols, long CB, long SO,
+                          long SI, const void *tw, const void *twq, int inv, double scale, hipStream_t s) {
+    // kind: 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III
+    const int kind = (inv ? 2 : 0) + (basis == 1 ? 1 : 0);
+    R2RArgs a{src, dst, ncols, CB, SO, SI, tw, twq, kind, scale};
+    k->fn(a, s);
+    return launch_check("sine/cosine pass");
+}
+
 tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s) {
     const long nzh = ax.nz / 2 + 1;
+    if (ax.by != 0)
+        return r2r_pass(ax.ry, ax.by, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, ax.twqy,
+                        inv, 1.0, s);
     return strided_pass(ax.ky, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, inv, 1.0, s);
 }
 
@@ -59,7 +71,36 @@ tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields
                      hipStream_t s) {
     const long nzh = ax.nz / 2 + 1;
     const long cb = (long)ax.ny * nzh;
+    if (ax.bx != 0)
+        return r2r_pass(ax.rx, ax.bx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, ax.twqx, inv, scale,
+                        s);
     return strided_pass(ax.kx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, inv, scale, s);
+}
+
+tk_status axes_set_basis(FftAxes *ax, int bx, int by) {
+    if (bx < 0 || bx > 2 || by < 0 || by > 2) return fail(TK_EINVAL, "basis must be 0 (Fourier), 1 (sine), 2 (cosine)");
+    ax->bx = bx;
+    ax->by = by;
+    tk_status st;
+    for (int axis = 0; axis < 2; ++axis) {
+        const int b = axis == 0 ? bx : by;
+        if (!b) continue;
+        const int L = axis == 0 ? ax->nx : ax->ny;
+        const R2RKernel *k = nullptr;
+        for (const auto &q : r2r_kernels())
+            if (q.L == L && q.dt == ax->dt) k = &q;
+        if (!k) return fail(TK_EUNSUPPORTED, "no sine/cosine kernel for length %d", L);
+        const void *tq = twiddle_table(4 * L, ax->dt, &st);
+        if (!tq) return st;
+        if (axis == 0) {
+            ax->rx = k;
+            ax->twqx = tq;
+        } else {
+            ax->ry = k;
+            ax->twqy = tq;
+        }
+    }
+    return TK_OK;
 }
 
 tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s) {
@@ -160,6 +201,17 @@ extern "C" tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz,
     }
     *plan = p;
     return TK_OK;
+}
+
+extern "C" tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
+                                             int basis_x, int basis_y, unsigned flags) {
+    TK_TRY(fft3d_plan_create(plan, nx, ny, nz, batch, dt, flags));
+    tk_status st = axes_set_basis(&(*plan)->ax, basis_x, basis_y);
+    if (st != TK_OK) {
+        fft3d_plan_destroy(*plan);
+        *plan = nullptr;
+    }
+    return st;
 }
 
 extern "C" tk_status fft3d_workspace_size(tk_fft3d_t p, size_t *bytes) {

@@ -12,9 +12,15 @@ struct FftAxes {
     const void *twx, *twy, *twz;
     const StridedKernel *kx, *ky;
     const ZKernel *kz;
+    // bases along x and y: 0 Fourier, 1 sine, 2 cosine (z is always Fourier)
+    int bx = 0, by = 0;
+    const R2RKernel *rx = nullptr, *ry = nullptr;
+    const void *twqx = nullptr, *twqy = nullptr;
 };
 
 tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_tune);
+// Sine / cosine bases along x and/or y (after axes_init).
+tk_status axes_set_basis(FftAxes *ax, int bx, int by);
 // want_W / want_nt = 0 selects the default candidate.
 const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E);
 const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E);

@@ -58,6 +58,27 @@ struct ZKernel {
 const std::vector<StridedKernel> &strided_kernels();
 const std::vector<ZKernel> &z_kernels();
 
+// Sine / cosine transforms along a strided axis (same column addressing as StridedArgs).
+struct R2RArgs {
+    const void *src;
+    void *dst;
+    long ncols, CB, SO, SI;
+    const void *tw;   // W_L^j
+    const void *twq;  // W_{4L}^j, j < L
+    int kind;         // 0 DCT-II, 1 DST-II (forward), 2 DCT-III, 3 DST-III (inverse)
+    double scale;
+};
+using R2RFn = void (*)(const R2RArgs &, hipStream_t);
+struct R2RKernel {
+    int L;
+    tk_dtype dt;
+    int W, E;
+    R2RFn fn;
+};
+const std::vector<R2RKernel> &r2r_kernels();
+
+#define TK_FOR_EACH_LEN(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
 // ---- strided complex pass ----------------------------------------------------------------------
 template <int L, int E, int W> constexpr int strided_es() { return W + 1; }
 
