@@ -121,16 +121,15 @@ def kernel_names(desc, n):
     """Template names of the six pass kernels from the plan's tile descriptions."""
     import re
     z = re.search(r"LPW=(\d+) E=(\d+)", desc[0])
-    y = re.search(r"W=(\d+) E=(\d+)", desc[1])
-    x = re.search(r"W=(\d+) E=(\d+)", desc[2])
     names = {}
     if z:
         names["z_r2c"] = "k_z_r2c<float, %d, %s, %s>" % (n // 2, z.group(2), z.group(1))
         names["z_c2r"] = "k_z_c2r<float, %d, %s, %s>" % (n // 2, z.group(2), z.group(1))
-    if y:
-        names["y_fwd"] = names["y_inv"] = "k_strided<float, %d, %s, %s>" % (n, y.group(2), y.group(1))
-    if x:
-        names["x_fwd"] = names["x_inv"] = "k_strided<float, %d, %s, %s>" % (n, x.group(2), x.group(1))
+    for p, keys in ((1, ("y_fwd", "y_inv")), (2, ("x_fwd", "x_inv"))):
+        m = re.search(r"W=(\d+) E=(\d+) v=(\d+)", desc[p])
+        if m:
+            kern = "k_strided_pp" if m.group(3) == "1" else "k_strided"
+            names[keys[0]] = names[keys[1]] = "%s<float, %d, %s, %s, false>" % (kern, n, m.group(2), m.group(1))
     return names
 
 

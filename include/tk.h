@@ -139,16 +139,31 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
                          int report_len);
 
 /* Force the tile of (L, dt, pass): pass 0 = Z (a = threads per workgroup), 1 = Y and
- * 2 = X (a = columns per tile); E = points per thread.  a <= 0 removes the entry.
- * TK_EUNSUPPORTED if no such tile is compiled. */
-tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E);
+ * 2 = X (a = columns per tile); E = points per thread; variant (strided passes; 0 for Z)
+ * 0 = one tile per workgroup, 1..3 = persistent workgroups that issue the next tile's loads
+ * before transforming the current one (1: tiles dealt round-robin, 2: round-robin with a
+ * contiguous run per XCD, 3: consecutive tiles per workgroup).  Passes 3, 4, 5 are the
+ * solver passes P1 (a = columns), P3 (a = lines per workgroup) and P5 (a = columns) of an
+ * L^3 grid (variant 1: the tile compiled for two workgroups per CU), pass 6 the solver's
+ * Y passes P2 / P4 (a strided tile as for pass 1); solver handles created afterwards use
+ * them.  a <= 0 removes the entry.  TK_EUNSUPPORTED if no such tile is compiled. */
+tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant);
+
+/* Autotune the solver passes P1, P2 / P4, P3 and P5 of an n^3 grid in dtype dt: every
+ * compiled tile variant runs on pseudo-random fields of the grid's size, is admitted only
+ * if its output matches the first variant's to relative L2 1e-5 (FP32) / 1e-12 (FP64),
+ * and is timed (median of iters launches); the fastest admitted variant of each pass goes
+ * into the tile table (passes 3, 4, 5, 6).  Allocates 18 spectral fields for the duration
+ * of the call.
+ * report (may be NULL) receives one text line per variant.  Synchronises. */
+tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, int report_len);
 
 /* Forget every tuned tile. */
 tk_status fft3d_tune_clear(void);
 
 /* Number of compiled tile candidates of (L, dt, pass); the first `cap` are written to
- * a[] and E[] (either may be NULL). */
-int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int cap);
+ * a[], E[] and variant[] (any may be NULL). */
+int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int *variant, int cap);
 
 /* ------------------------------------------------------------------------------------
  * Pseudo-spectral incompressible Navier-Stokes in the periodic (2 pi)^3 box.

@@ -59,9 +59,10 @@ def _declare(L):
         "fft3d_describe": ([vp, i, ctypes.c_char_p, i], i),
         "fft3d_plan_destroy": ([vp], i),
         "fft3d_autotune": ([i, i, i, i, i, i, ctypes.c_char_p, i], i),
-        "fft3d_tune_set": ([i, i, i, i, i], i),
+        "fft3d_tune_set": ([i, i, i, i, i, i], i),
         "fft3d_tune_clear": ([], i),
-        "fft3d_tile_candidates": ([i, i, i, P(i), P(i), i], i),
+        "ns_autotune": ([i, i, i, ctypes.c_char_p, i], i),
+        "fft3d_tile_candidates": ([i, i, i, P(i), P(i), P(i), i], i),
         "ns_create": ([P(vp), P(NsConfig)], i),
         "ns_rhs": ([vp, vp, vp, vp], i),
         "ns_step": ([vp, vp, d, i, P(d), vp], i),
@@ -156,19 +157,30 @@ def autotune(nx, ny=None, nz=None, batch=1, dtype=None, iters=5):
     return buf.value.decode()
 
 
+def ns_autotune(n, iters=5, dtype=None):
+    """Time every compiled variant of the solver passes P1, P3, P5 of an n^3 grid and record
+    the fastest one that matches variant 0 (see ns_autotune).  Returns the text report."""
+    import torch
+    buf = ctypes.create_string_buffer(1 << 14)
+    check(lib().ns_autotune(n, _dtype_code(dtype or torch.float32), iters, buf, 1 << 14))
+    return buf.value.decode()
+
+
 def tile_candidates(L, dtype, pass_):
-    """[(a, E)] compiled tile candidates of (L, dtype, pass): pass 0 = Z (a = threads),
-    1 = Y and 2 = X (a = columns per tile)."""
+    """[(a, E, v)] compiled tile candidates of (L, dtype, pass): pass 0 = Z (a = threads),
+    1 = Y and 2 = X (a = columns per tile), v = 1 for the persistent strided variant;
+    passes 3, 4, 5 = solver P1, P3, P5 of an L^3 grid."""
     code = _dtype_code(dtype)
-    n = lib().fft3d_tile_candidates(L, code, pass_, None, None, 0)
+    n = lib().fft3d_tile_candidates(L, code, pass_, None, None, None, 0)
     a = (ctypes.c_int * max(n, 1))()
     e = (ctypes.c_int * max(n, 1))()
-    lib().fft3d_tile_candidates(L, code, pass_, a, e, n)
-    return [(a[i], e[i]) for i in range(n)]
+    v = (ctypes.c_int * max(n, 1))()
+    lib().fft3d_tile_candidates(L, code, pass_, a, e, v, n)
+    return [(a[i], e[i], v[i]) for i in range(n)]
 
 
-def tune_set(L, dtype, pass_, a, E):
-    check(lib().fft3d_tune_set(L, _dtype_code(dtype), pass_, a, E))
+def tune_set(L, dtype, pass_, a, E, v=0):
+    check(lib().fft3d_tune_set(L, _dtype_code(dtype), pass_, a, E, v))
 
 
 def tune_clear():
@@ -176,11 +188,11 @@ def tune_clear():
 
 
 def tune_save(path, entries):
-    """Persist tuned tiles [(L, dtype_code, pass, a, E)] as JSON lines."""
+    """Persist tuned tiles [(L, dtype_code, pass, a, E, v)] as JSON lines."""
     import json
     with open(path, "w") as f:
-        for L, dt, p, a, E in entries:
-            f.write(json.dumps({"L": L, "dtype": dt, "pass": p, "a": a, "E": E}) + "\n")
+        for L, dt, p, a, E, v in entries:
+            f.write(json.dumps({"L": L, "dtype": dt, "pass": p, "a": a, "E": E, "v": v}) + "\n")
 
 
 def tune_load(path):
@@ -191,7 +203,7 @@ def tune_load(path):
         for line in f:
             if line.strip():
                 e = json.loads(line)
-                check(lib().fft3d_tune_set(e["L"], e["dtype"], e["pass"], e["a"], e["E"]))
+                check(lib().fft3d_tune_set(e["L"], e["dtype"], e["pass"], e["a"], e["E"], e.get("v", 0)))
                 n += 1
     return n
 

@@ -88,6 +88,30 @@ const void *twiddle_table(int n, tk_dtype dt, tk_status *st) {
     return p;
 }
 
+int resident_groups(const void *kernel, int nt) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_tuple(dev, kernel, nt);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    // a failed query (it has been seen to fail for kernels that use accumulation registers)
+    // must not leave its error for the caller's next launch check: clear it and assume one
+    // workgroup per CU, which any launchable kernel reaches
+    int cus = 0, occ = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, nt, 0) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    return cache[key] = occ * cus;
+}
+
 #define TK_REG(name) void name(std::vector<StridedKernel> &s, std::vector<ZKernel> &z);
 TK_REG(register_f32_a) TK_REG(register_f32_b) TK_REG(register_f32_c) TK_REG(register_f32_d)
 TK_REG(register_f32_e) TK_REG(register_f32_f) TK_REG(register_f64_a) TK_REG(register_f64_b)

@@ -16,14 +16,15 @@ namespace tk {
 
 // Default tile: the widest W (longest contiguous runs) whose LDS tile still lets two
 // workgroups share a CU; ties go to fewer threads.
-const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E) {
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E, int want_v) {
     const StridedKernel *best = nullptr;
     for (const auto &k : strided_kernels()) {
         if (k.L != L || k.dt != dt) continue;
         if (want_W > 0) {
-            if (k.W == want_W && k.E == want_E) return &k;
+            if (k.W == want_W && k.E == want_E && k.var == want_v) return &k;
             continue;
         }
+        if (k.var != 0) continue;
         auto score = [](const StridedKernel &q) { return (q.lds <= 81920 ? 100000 : 0) + q.W * 10 - q.nt / 256; };
         if (!best || score(k) > score(*best)) best = &k;
     }
@@ -43,10 +44,27 @@ const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E) {
     return best;
 }
 
+// The strided kernels address a tile's points as a 64-bit base shared by the workgroup
+// plus a 32-bit byte offset per thread, which spans the planes of SO elements a tile
+// touches and TPL rows of SI.  When that exceeds 32 bits (several 1024^3 members in one
+// call) the pass is launched once per plane, where a tile never crosses a plane.
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
                        long SI, const void *tw, int inv, double scale, hipStream_t s) {
-    StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale, -1, -1};
-    k->fn(a, s);
+    const long esz = k->dt == TK_F32 ? 8 : 16;
+    const long in_plane = (CB + (long)(k->L / k->E) * SI) * esz;
+    const long crossing = ((k->W + CB - 2) / CB) * SO * esz;
+    const long lim = 1L << 32;
+    if (in_plane + crossing < lim) {
+        StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale, -1, -1};
+        k->fn(a, s);
+        return launch_check("strided pass");
+    }
+    if (in_plane >= lim) return fail(TK_EUNSUPPORTED, "strided pass: a plane spans more than 4 GB");
+    for (long p = 0; p < ncols / CB; ++p) {
+        StridedArgs a{(const char *)src + p * SO * esz, (char *)dst + p * SO * esz, CB, CB, SO, SI, tw, inv, scale,
+                      -1, -1};
+        k->fn(a, s);
+    }
     return launch_check("strided pass");
 }
 
@@ -136,10 +154,10 @@ tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_t
         tx = tuned_tile(nx, dt, 2);
         tz = tuned_tile(nz, dt, 0);
     }
-    ax->ky = pick_strided(ny, dt, ty.a, ty.E);
-    if (!ax->ky) ax->ky = pick_strided(ny, dt, 0, 0);
-    ax->kx = pick_strided(nx, dt, tx.a, tx.E);
-    if (!ax->kx) ax->kx = pick_strided(nx, dt, 0, 0);
+    ax->ky = pick_strided(ny, dt, ty.a, ty.E, ty.v);
+    if (!ax->ky) ax->ky = pick_strided(ny, dt, 0, 0, 0);
+    ax->kx = pick_strided(nx, dt, tx.a, tx.E, tx.v);
+    if (!ax->kx) ax->kx = pick_strided(nx, dt, 0, 0, 0);
     ax->kz = pick_z(nz, dt, tz.a, tz.E);
     if (!ax->kz) ax->kz = pick_z(nz, dt, 0, 0);
     if (!ax->kx || !ax->ky || !ax->kz) return fail(TK_EUNSUPPORTED, "no kernel for %dx%dx%d", nx, ny, nz);
@@ -330,8 +348,8 @@ extern "C" tk_status fft3d_describe(tk_fft3d_t p, int pass, char *buf, int len) 
         n = snprintf(buf, len, "z N=%d LPW=%d E=%d nt=%d lds=%d", ax.nz, ax.kz->LPW, ax.kz->E, ax.kz->nt, ax.kz->lds);
     else if (pass == 1 || pass == 2) {
         const StridedKernel *k = pass == 1 ? ax.ky : ax.kx;
-        n = snprintf(buf, len, "%c L=%d W=%d E=%d nt=%d lds=%d", pass == 1 ? 'y' : 'x', k->L, k->W, k->E, k->nt,
-                     k->lds);
+        n = snprintf(buf, len, "%c L=%d W=%d E=%d v=%d nt=%d lds=%d", pass == 1 ? 'y' : 'x', k->L, k->W, k->E, k->var,
+                     k->nt, k->lds);
     } else
         return fail(TK_EINVAL, "pass must be 0, 1 or 2");
     (void)n;

@@ -22,7 +22,7 @@ tk_status axes_init(FftAxes *ax, int nx, int ny, int nz, tk_dtype dt, bool use_t
 // Sine / cosine bases along x and/or y (after axes_init).
 tk_status axes_set_basis(FftAxes *ax, int bx, int by);
 // want_W / want_nt = 0 selects the default candidate.
-const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E);
+const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E, int want_v);
 const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E);
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
                        long SI, const void *tw, int inv, double scale, hipStream_t s);

@@ -149,12 +149,26 @@ template <int ES> __device__ __forceinline__ int lds_at(int e) {
 }
 template <int L> constexpr int lds_line_len() { return L + (L >> 5) + 1; }
 
+// ---- synchronisation of the exchanges ------------------------------------------------------------
+// A contiguous line (ES == 1) is handled by TPL consecutive lanes of one wavefront (TPL
+// divides 64) and owns its LDS row, so its exchanges only have to be ordered within the
+// wavefront: the LDS executes a wavefront's instructions in order, and waiting for the
+// wavefront's own LDS operations (lgkmcnt 0) behind a compiler memory barrier is enough.
+// Waves of a workgroup then run their lines independently instead of meeting at a
+// workgroup barrier twice per stage.  Column tiles spread a line over several waves and
+// use the workgroup barrier.
+template <int ES> __device__ __forceinline__ void exchange_sync() {
+    if constexpr (ES == 1) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else __syncthreads();
+}
+
 // ---- the transform -------------------------------------------------------------------------------
 // v[i] = x[jt + i TPL] on entry, X[jt + i TPL] on exit (forward DFT, unscaled).
 // d: this line's LDS (element e at d[lds_at<ES>(e)]), tw: LDS table with W_L^j at
 // tw[j * TS].
-// Every thread of the workgroup must call it (it contains barriers).  On exit the LDS
-// line may be reused only after a barrier.
+// Column tiles (ES > 1): every thread of the workgroup must call it (it contains
+// barriers); on exit the LDS may be reused only after a barrier.  Contiguous lines
+// (ES == 1): the lanes of a line call it together and may reuse their LDS row at once.
 template <typename T, int L, int E, int ES, int TS = 1, int S = 0>
 __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw) {
     using C = V2<T>;
@@ -163,6 +177,7 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
     constexpr int NS = rplan_span(P, S);
     constexpr int NB = E / R;
     constexpr int TPL = L / E;
+    static_assert(ES != 1 || (TPL <= 64 && 64 % TPL == 0), "a contiguous line must sit inside one wavefront");
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = jt + b * TPL;
@@ -182,10 +197,10 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
 #pragma unroll
             for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
         }
-        __syncthreads();
+        exchange_sync<ES>();
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
-        __syncthreads();
+        exchange_sync<ES>();
         line_fft<T, L, E, ES, TS, S + 1>(v, d, jt, tw);
     }
 }

@@ -32,11 +32,14 @@ struct StridedArgs {
 };
 using StridedFn = void (*)(const StridedArgs &, hipStream_t);
 
+// var 0: one tile per workgroup; var 1..3: persistent workgroups with the next tile's loads
+// issued ahead (k_strided_pp), tile order var.
 struct StridedKernel {
     int L;
     tk_dtype dt;
     int W, E, nt, lds;
     StridedFn fn;
+    int var;
 };
 
 struct ZArgs {
@@ -84,46 +87,99 @@ template <int L, int E, int W> constexpr int strided_es() { return W + 1; }
 
 __device__ __forceinline__ bool row_kept(int r, int L, int k) { return k < 0 || r <= k || r >= L - k; }
 
-// One column tile: W columns x L points.  lds: L (W + 1) complex for the exchanges;
-// tw: the W_L^j table already in LDS.  Contains barriers: every thread calls it.
-template <typename T, int L, int E, int W>
-__device__ __forceinline__ void strided_tile(const V2<T> *src, V2<T> *dst, long ncols, long CB, long SO, long SI,
-                                             int inv, T scale, int kl, int ks, long tile, V2<T> *lds,
-                                             const V2<T> *tw) {
-    using C = V2<T>;
+// Addressing of one column tile (columns c0 .. c0 + width - 1, width <= W) for thread
+// (col, jt) = (tid % W, tid / W), which handles the points x[jt + i TPL] of column c0 + col:
+// point i sits at element tb + i TPL SI + lo / sizeof(C), where tb (the tile's first
+// element) is uniform over the workgroup and lo is a 32-bit byte offset, so a load is one
+// scalar base plus one vector offset and a thread keeps a single address register.
+// lo < 2^31 for every supported grid: a tile spans at most (W - 1) / CB + 2 planes of SO
+// elements plus L rows of SI, under 300 MB for lengths up to 1024.  Lanes outside the
+// tile get lo = 0 (a valid address whose value they discard).
+struct TileAddr {
+    long tb;
+    unsigned lo;
+    bool valid;
+};
+
+template <typename T, int W>
+__device__ __forceinline__ TileAddr tile_addr(long c0, int width, long ncols, long CB, long SO, long SI) {
+    const int col = threadIdx.x % W;
+    const int jt = threadIdx.x / W;
+    const long c = c0 + col;
+    const bool valid = col < width && c < ncols;
+    const long tb = (c0 / CB) * SO + c0 % CB;
+    const long e = valid ? (c / CB) * SO + c % CB - tb + (long)jt * SI : 0;
+    return {tb, (unsigned)(e * (long)sizeof(V2<T>)), valid};
+}
+
+template <typename P> __device__ __forceinline__ const P *at_bytes(const P *p, unsigned lo) {
+    return reinterpret_cast<const P *>(reinterpret_cast<const char *>(p) + lo);
+}
+template <typename P> __device__ __forceinline__ P *at_bytes(P *p, unsigned lo) {
+    return reinterpret_cast<P *>(reinterpret_cast<char *>(p) + lo);
+}
+
+// v[i] = x[jt + i TPL] of the thread's column.  MASK: rows outside the kl mask (and
+// columns outside the tile) read as zero without touching memory.  Without MASK every
+// row is read, branch-free: a lane outside the tile reads the tile's first column and
+// transforms it in its own LDS column, and its result is never stored.
+template <typename T, int L, int E, int W, bool MASK>
+__device__ __forceinline__ void strided_load(V2<T> (&v)[E], const V2<T> *src, const TileAddr &a, long SI,
+                                             int kl) {
     constexpr int TPL = L / E;
-    constexpr int ES = strided_es<L, E, W>();
-    const int tid = threadIdx.x;
-    const int col = tid % W;
-    const int jt = tid / W;
-    const long c = tile * W + col;
-    const bool valid = c < ncols;
-    const long base = valid ? (c / CB) * SO + (c % CB) : 0;
-    C v[E];
+    const int jt = threadIdx.x / W;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int r = jt + i * TPL;
-        C x = (valid && row_kept(r, L, kl)) ? src[base + (long)r * SI] : mk<T>(0, 0);
-        if (inv) x.y = -x.y;
-        v[i] = x;
-    }
-    line_fft<T, L, E, ES>(v, lds + col, jt, tw);
-    if (valid) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int r = jt + i * TPL;
-            C x = v[i];
-            if (inv) x.y = -x.y;
-            x.x *= scale;
-            x.y *= scale;
-            if (row_kept(r, L, ks)) dst[base + (long)r * SI] = x;
+        const V2<T> *row = src + a.tb + (long)(i * TPL) * SI;
+        if constexpr (MASK) {
+            v[i] = (a.valid && row_kept(jt + i * TPL, L, kl)) ? *at_bytes(row, a.lo) : mk<T>(0, 0);
+        } else {
+            v[i] = *at_bytes(row, a.lo);
         }
     }
 }
 
+// Stores of the transformed points, conjugated back for the inverse and scaled; with
+// MASK only rows inside the ks mask are written.
+template <typename T, int L, int E, int W, bool MASK>
+__device__ __forceinline__ void strided_store(const V2<T> (&v)[E], V2<T> *dst, const TileAddr &a, long SI, int inv,
+                                              T scale, int ks) {
+    constexpr int TPL = L / E;
+    const int jt = threadIdx.x / W;
+    if (!a.valid) return;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        V2<T> x = v[i];
+        if (inv) x.y = -x.y;
+        x.x *= scale;
+        x.y *= scale;
+        V2<T> *row = dst + a.tb + (long)(i * TPL) * SI;
+        if (!MASK || row_kept(jt + i * TPL, L, ks)) *at_bytes(row, a.lo) = x;
+    }
+}
+
+// One column tile: W columns x L points.  lds: L (W + 1) complex for the exchanges;
+// tw: the W_L^j table already in LDS.  Contains barriers: every thread calls it.
+template <typename T, int L, int E, int W, bool MASK = true>
+__device__ __forceinline__ void strided_tile(const V2<T> *src, V2<T> *dst, long ncols, long CB, long SO, long SI,
+                                             int inv, T scale, int kl, int ks, long tile, V2<T> *lds,
+                                             const V2<T> *tw) {
+    using C = V2<T>;
+    constexpr int ES = strided_es<L, E, W>();
+    const TileAddr a = tile_addr<T, W>(tile * W, W, ncols, CB, SO, SI);
+    C v[E];
+    strided_load<T, L, E, W, MASK>(v, src, a, SI, kl);
+    if (inv) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
+    }
+    line_fft<T, L, E, ES>(v, lds + threadIdx.x % W, threadIdx.x / W, tw);
+    strided_store<T, L, E, W, MASK>(v, dst, a, SI, inv, scale, ks);
+}
+
 template <typename T, int L, int E, int W> constexpr int strided_lds_elems() { return L * strided_es<L, E, W>(); }
 
-template <typename T, int L, int E, int W>
+template <typename T, int L, int E, int W, bool MASK>
 __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                          long SO, long SI, const V2<T> *__restrict__ twg,
                                                          int inv, T scale, int kl, int ks) {
@@ -133,16 +189,106 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> 
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, NT);
     __syncthreads();
-    strided_tile<T, L, E, W>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks, xcd_tile(blockIdx.x, gridDim.x), lds,
-                             tw);
+    strided_tile<T, L, E, W, MASK>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks,
+                                   xcd_tile(blockIdx.x, gridDim.x), lds, tw);
 }
 
+// Row masks select the MASK instantiation; plain transforms run the branch-free one.
 template <typename T, int L, int E, int W>
 void launch_strided(const StridedArgs &a, hipStream_t s) {
     constexpr int NT = W * (L / E);
     unsigned nb = cdiv(a.ncols, W);
-    hipLaunchKernelGGL((k_strided<T, L, E, W>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src, (V2<T> *)a.dst,
-                       a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl, a.ks);
+    if (a.kl >= 0 || a.ks >= 0)
+        hipLaunchKernelGGL((k_strided<T, L, E, W, true>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
+                           (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
+                           a.ks);
+    else
+        hipLaunchKernelGGL((k_strided<T, L, E, W, false>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
+                           (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
+                           a.ks);
+}
+
+// ---- persistent strided pass ----------------------------------------------------------------------
+// G workgroups (as many as are resident on the chip at once) share the tiles: each takes q
+// full tiles, then at most one narrow tail tile of wt columns, so the columns left after
+// the last full round are spread over every workgroup instead of idling most of the chip
+// behind a few whole tiles.  The loads of the next tile are issued before the current
+// tile's transform: a workgroup barrier waits for LDS traffic only, so they stay in flight
+// across the exchanges.  Tiles of a workgroup never share columns, so an in-place pass
+// stays correct.  The order in which the tiles are dealt decides which columns are in
+// flight together, and with it how well the rows' DRAM pages and the XCDs' L2s are used;
+// the best one depends on the row pitch, so it is a tuning choice:
+//   order 1: round k takes tiles k G .. k G + G - 1, workgroup g the (k G + g)-th;
+//   order 2: as 1, with the workgroups numbered XCD by XCD (they are dealt to the 8 XCDs
+//            in turn), so each XCD takes a contiguous run of a round's tiles;
+//   order 3: workgroup g takes the consecutive tiles g q .. g q + q - 1.
+template <typename T, int L, int E, int W, bool MASK>
+__global__ __launch_bounds__(W *(L / E)) void k_strided_pp(const V2<T> *src, V2<T> *dst, long ncols, long CB,
+                                                            long SO, long SI, const V2<T> *__restrict__ twg,
+                                                            int inv, T scale, int kl, int ks, long q, int wt,
+                                                            int ntail, int order) {
+    using C = V2<T>;
+    constexpr int NT = W * (L / E);
+    constexpr int ES = strided_es<L, E, W>();
+    __shared__ C lds[strided_lds_elems<T, L, E, W>()];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, NT);
+    __syncthreads();
+    const long G = gridDim.x;
+    const long g = (order == 2 && (G & 7) == 0) ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const long nu = q + (g < ntail ? 1 : 0);
+    auto addr_of = [&](long k) {
+        return k < q ? tile_addr<T, W>((order == 3 ? g * q + k : k * G + g) * W, W, ncols, CB, SO, SI)
+                     : tile_addr<T, W>(q * G * W + g * wt, wt, ncols, CB, SO, SI);
+    };
+    C nx[E];
+    TileAddr an = addr_of(0);
+    if (nu > 0) strided_load<T, L, E, W, MASK>(nx, src, an, SI, kl);
+    for (long k = 0; k < nu; ++k) {
+        const TileAddr a = an;
+        C v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = nx[i];
+        if (k + 1 < nu) {
+            an = addr_of(k + 1);
+            strided_load<T, L, E, W, MASK>(nx, src, an, SI, kl);
+        }
+        if (inv) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
+        }
+        line_fft<T, L, E, ES>(v, lds + threadIdx.x % W, threadIdx.x / W, tw);
+        strided_store<T, L, E, W, MASK>(v, dst, a, SI, inv, scale, ks);
+    }
+}
+
+// Number of workgroups of `kernel` (nt threads) resident on the current device at once.
+int resident_groups(const void *kernel, int nt);
+
+template <typename T, int L, int E, int W, int ORDER>
+void launch_strided_pp(const StridedArgs &a, hipStream_t s) {
+    constexpr int NT = W * (L / E);
+    const bool mask = a.kl >= 0 || a.ks >= 0;
+    const void *kp = mask ? reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, true>)
+                          : reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, false>);
+    const long G = resident_groups(kp, NT);
+    const long q = (a.ncols / W) / G;
+    const long left = a.ncols - q * G * W;
+    int wt = W, ntail = 0;
+    if (left > 0) {
+        long w = (left + G - 1) / G;
+        w = (w + 7) / 8 * 8;
+        wt = (int)(w < W ? w : W);
+        ntail = (int)((left + wt - 1) / wt);
+    }
+    if (mask)
+        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, true>), dim3((unsigned)G), dim3(NT), 0, s, (const V2<T> *)a.src,
+                           (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
+                           a.ks, q, wt, ntail, ORDER);
+    else
+        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, false>), dim3((unsigned)G), dim3(NT), 0, s,
+                           (const V2<T> *)a.src, (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw,
+                           a.inv, (T)a.scale, a.kl, a.ks, q, wt, ntail, ORDER);
 }
 
 // ---- Z pass: real lines <-> half spectra ----------------------------------------------------------

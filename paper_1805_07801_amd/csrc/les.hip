@@ -488,7 +488,7 @@ static tk_status les_steps(tk_ns_t p, const tk_mlp *w, void *u, int nsteps, hipS
         if (w) TK_TRY(les_closure(p, w, u, s));
         a.add3 = w ? p->les.add3 : nullptr;
         a.mode = RK2_S1;
-        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
         if (w) TK_TRY(les_closure(p, w, p->ust, s));
         a.mode = RK2_S2;
         TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "ns_api.hpp"
+#include "tune.hpp"
 
 namespace tk {
 
@@ -36,35 +37,48 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
     for (const auto &k : ns_kernels())
         if (k.N == n && k.dt == dt) g->nk = &k;
     if (!g->nk) return fail(TK_EUNSUPPORTED, "no solver kernels for n=%d", n);
+    auto pick = [&](int pass, auto *v, int nv) {
+        const TileChoice c = tuned_tile(n, dt, pass);
+        for (int i = 0; i < nv; ++i)
+            if (v[i].a == c.a && v[i].E == c.E && v[i].v == c.v) return i;
+        return 0;
+    };
+    g->v1 = pick(3, g->nk->p1v, g->nk->np1);
+    g->v3 = pick(4, g->nk->p3v, g->nk->np3);
+    g->v5 = pick(5, g->nk->p5v, g->nk->np5);
+    const TileChoice cy = tuned_tile(n, dt, 6);
+    g->ky = cy.a > 0 ? pick_strided(n, dt, cy.a, cy.E, cy.v) : nullptr;
+    if (!g->ky) g->ky = g->ax.ky;
     return TK_OK;
 }
 
-tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, unsigned *umax,
+tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
                       NsState *st_set, hipStream_t s) {
     const int n = g.n;
     const long nzh = n / 2 + 1;
     // P1: x-inverse of u^ and omega^ = i k x u^
-    g.nk->p1(uin, w6, g.K, g.KZC, g.ax.twx, s);
+    g.nk->p1v[g.v1].fn(uin, w6, g.K, g.KZC, g.ax.twx, s);
     TK_TRY(launch_check("ns P1"));
     // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
     StridedArgs y2{w6, w6, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
-    g.ax.ky->fn(y2, s);
+    g.ky->fn(y2, s);
     TK_TRY(launch_check("ns P2"));
     // P3: z fused c2r -> u x omega -> r2c
-    g.nk->p3(w6, (long)n * n, g.KZC, g.ax.twz, umax, s);
+    g.nk->p3v[g.v3].fn(w6, (long)n * n, g.KZC, g.ax.twz, part, s);
     TK_TRY(launch_check("ns P3"));
     if (st_set) {
-        hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(64), 0, s, st_set);
+        const int nparts = (int)cdiv((long)n * n, g.nk->p3v[g.v3].a);
+        hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(1024), 0, s, st_set, part, nparts);
         TK_TRY(launch_check("ns step size"));
     }
     // P4: y-forward of the 3 products, kept ky rows written
     StridedArgs y4{w6, w6, 3L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 0, 1.0, -1, g.K};
-    g.ax.ky->fn(y4, s);
+    g.ky->fn(y4, s);
     TK_TRY(launch_check("ns P4"));
     // P5: x-forward, projection, stage combine
     P5Args a = p5;
     a.c3 = w6;
-    g.nk->p5(a, g.K, g.KZC, g.ax.twx, s);
+    g.nk->p5v[g.v5].fn(a, g.K, g.KZC, g.ax.twx, s);
     return launch_check("ns P5");
 }
 
@@ -111,6 +125,7 @@ static void ns_free(tk_ns_s *p) {
     if (p->aux) hipFree(p->aux);
     if (p->ust) hipFree(p->ust);
     if (p->st) hipFree(p->st);
+    if (p->umax_part) hipFree(p->umax_part);
     if (p->dscratch) hipFree(p->dscratch);
     delete p;
 }
@@ -136,6 +151,7 @@ extern "C" tk_status ns_create(tk_ns_t *out, const ns_config *cfg) {
     const size_t dbytes = sizeof(double) * ((size_t)(NS_DIAG_BLOCKS + 2) * (NS_DIAG_HEAD + p->nshell));
     if (hipMalloc(&p->w6, 6 * p->fbytes) != hipSuccess || hipMalloc(&p->aux, 3 * p->fbytes) != hipSuccess ||
         hipMalloc(&p->ust, 3 * p->fbytes) != hipSuccess || hipMalloc((void **)&p->st, sizeof(NsState)) != hipSuccess ||
+        hipMalloc((void **)&p->umax_part, sizeof(float) * cfg->n * cfg->n) != hipSuccess ||
         hipMalloc((void **)&p->dscratch, dbytes) != hipSuccess) {
         ns_free(p);
         return fail(TK_ENOMEM, "solver workspace allocation (%zu bytes) failed", 12 * p->fbytes);
@@ -161,12 +177,12 @@ static tk_status ns_one_step(tk_ns_s *p, void *u, hipStream_t s) {
     a.nu = p->cfg.nu;
     if (p->cfg.scheme == 0) {
         a.mode = RK2_S1;
-        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
         a.mode = RK2_S2;
         TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
     } else {
         a.mode = RK4_S1;
-        TK_TRY(ns_rhs_eval(g, u, p->w6, a, &p->st->umax, p->st, s));
+        TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
         for (int m = RK4_S2; m <= RK4_S4; ++m) {
             a.mode = m;
             TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));

@@ -23,13 +23,16 @@ struct NsGrid {
     tk_dtype dt;
     FftAxes ax;
     const NsKernels *nk;
+    int v1, v3, v5;  // chosen variants of P1, P3, P5 (autotuner table, else 0)
+    const StridedKernel *ky;  // Y passes P2 / P4 (autotuner table pass 6, else the transform's)
 };
 tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
 
 // One right-hand side of input uin (3 fields) through P1..P5 with workspace w6 (6 fields);
-// P5 combines according to `mode` (see NsMode).  umax != null: P3 records max |u|_1 and,
-// when st_set != null, the step-size kernel runs after P3.
-tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, unsigned *umax,
+// P5 combines according to `mode` (see NsMode).  part != null (n^2 floats): P3 records
+// max |u|_1 per workgroup and, when st_set != null, the step-size kernel reduces them
+// after P3.
+tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
                       NsState *st_set, hipStream_t s);
 
 // Random solenoidal initial state from real noise [3][n][n][n] (see ns_init_random).
@@ -56,6 +59,7 @@ struct tk_ns_s {
     size_t fbytes;  // one spectral field
     void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
     tk::NsState *st = nullptr;
+    float *umax_part = nullptr;  // per-workgroup CFL maxima of P3 (n^2 floats)
     double *dscratch = nullptr;
     int nshell = 0;
     double last_dt = 0;

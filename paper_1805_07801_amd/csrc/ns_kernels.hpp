@@ -36,7 +36,7 @@ enum NsMode : int {
 struct NsState {
     double h;        // current step size
     double t;        // time (advanced by h at the start of each step)
-    unsigned umax;   // max over grid of |ux| + |uy| + |uz| (float bits), for the CFL step
+    unsigned umax;   // max over grid of |ux| + |uy| + |uz| (float bits): the ensemble's CFL step
     unsigned pad;
     double cfl_dx;   // cfl * 2 pi / N (0: fixed step)
     double hfix;     // fixed step size
@@ -78,6 +78,8 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
+    const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
     const T kyd = ka * (T)ky, kzd = ka * (T)((2 * kz == N) ? 0 : kz);
     constexpr int NOUT = RBC ? 7 : 6;
     C a0[E], a1[E], a2[E], a3[RBC ? E : 1];
@@ -85,11 +87,11 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
     for (int i = 0; i < E; ++i) {
         const int r = jt + i * TPL;
         const bool ld = valid && row_kept(r, L, K);
-        const long o = (long)r * RS + j;
-        a0[i] = ld ? u[o] : mk<T>(0, 0);
-        a1[i] = ld ? u[FS + o] : mk<T>(0, 0);
-        a2[i] = ld ? u[2 * FS + o] : mk<T>(0, 0);
-        if constexpr (RBC) a3[i] = ld ? u[3 * FS + o] : mk<T>(0, 0);
+        const long ro = (long)(i * TPL) * RS;
+        a0[i] = ld ? *at_bytes(u + ro, lo) : mk<T>(0, 0);
+        a1[i] = ld ? *at_bytes(u + FS + ro, lo) : mk<T>(0, 0);
+        a2[i] = ld ? *at_bytes(u + 2 * FS + ro, lo) : mk<T>(0, 0);
+        if constexpr (RBC) a3[i] = ld ? *at_bytes(u + 3 * FS + ro, lo) : mk<T>(0, 0);
     }
 #pragma unroll 1
     for (int f = 0; f < NOUT; ++f) {
@@ -114,15 +116,14 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
         }
         line_fft<T, L, E, ES>(v, lds + col, jt, tw);
         if (valid) {
-            V2<T> *dst = w6 + f * FS + j;
 #pragma unroll
-            for (int i = 0; i < E; ++i) dst[(long)(jt + i * TPL) * RS] = cconj(v[i]);
+            for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FS + (long)(i * TPL) * RS, lo) = cconj(v[i]);
         }
     }
 }
 
-template <typename T, int L, int E, int W, bool RBC = false>
-__global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
+template <typename T, int L, int E, int W, bool RBC = false, int WPE = 1>
+__global__ __launch_bounds__(W *(L / E)) __attribute__((amdgpu_waves_per_eu(WPE))) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
                                                        int KZC, const V2<T> *__restrict__ twg, T ka) {
     using C = V2<T>;
     __shared__ C lds[L * (W + 1)];
@@ -137,9 +138,12 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ 
 // transformed back, kz < KZC, into fields 0..2 of w6 (in place: each workgroup reads all
 // six fields of its lines before it writes).  lds: LPW lines of lds_line_len<L>().
 // RBC = true: a seventh input (temperature theta) gives three more outputs q = u theta.
+// CFL maximum of |u|_1 over the tile's samples: written to part[tile] (one value per
+// workgroup, reduced by the step-size kernel), else folded into *umax with one atomic per
+// workgroup; neither when both are null.
 template <typename T, int L, int E, int LPW, bool RBC = false>
 __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long tile, V2<T> *lds, const V2<T> *tw,
-                                           unsigned *umax) {
+                                           unsigned *umax, float *part = nullptr) {
     using C = V2<T>;
     constexpr int N = 2 * L;
     constexpr int NZH = L + 1;
@@ -157,15 +161,25 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     constexpr int NIN = RBC ? 7 : 6;
     constexpr int NOUT = RBC ? 6 : 3;
     C uu[3][E], c[NOUT][E];
-#pragma unroll
-    for (int f = 0; f < NIN; ++f) {
+    // the next field's samples are loaded before the current field is transformed, so the
+    // loads overlap the transform (the exchange waits only on LDS traffic)
+    auto load = [&](C(&x)[E], int f) {
         const C *s = w6 + f * FS + (valid ? l : 0) * NZH;
-        C v[E], xm[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
-            v[i] = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
+            x[i] = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
         }
+    };
+    C nx[E];
+    float umx = 0.f;  // lanes of invalid lines hold zeros
+    load(nx, 0);
+#pragma unroll
+    for (int f = 0; f < NIN; ++f) {
+        C v[E], xm[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = nx[i];
+        if (f + 1 < NIN) load(nx, f + 1);
         // X[L - k] from the mirror lane (X[L] itself is a masked mode: zero)
         mirror<T, L, E>(v, xm, jt);
 #pragma unroll
@@ -199,16 +213,13 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
                 for (int jj = 0; jj < 3; ++jj) c[3 + jj][i] = mk<T>(uu[jj][i].x * w.x, uu[jj][i].y * w.y);
             }
         }
-        if (f == 2 && umax) {  // CFL maximum of |u|_1 over the line's samples
-            float m = 0.f;
+        if (f == 2 && (umax || part)) {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const float s0 = (float)(fabs(uu[0][i].x) + fabs(uu[1][i].x) + fabs(uu[2][i].x));
                 const float s1 = (float)(fabs(uu[0][i].y) + fabs(uu[1][i].y) + fabs(uu[2][i].y));
-                m = fmaxf(m, fmaxf(s0, s1));
+                umx = fmaxf(umx, fmaxf(s0, s1));
             }
-            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-            if ((tid & 63) == 0 && valid) atomicMax(umax, __float_as_uint(m));
         }
     }
     // forward r2c of the products (unscaled; P5 applies 1/N^3)
@@ -235,17 +246,29 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             }
         }
     }
+    if (umax || part) {
+        __shared__ float wmax[16];
+        for (int o = 32; o > 0; o >>= 1) umx = fmaxf(umx, __shfl_xor(umx, o, 64));
+        if ((tid & 63) == 0) wmax[tid >> 6] = umx;
+        __syncthreads();
+        if (tid == 0) {
+            float m = wmax[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wmax[w]);
+            if (part) part[tile] = m;
+            else atomicMax(umax, __float_as_uint(m));
+        }
+    }
 }
 
 template <typename T, int L, int E, int LPW, bool RBC = false>
 __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, int KZC,
-                                                         const V2<T> *__restrict__ twg, unsigned *umax) {
+                                                         const V2<T> *__restrict__ twg, float *part) {
     using C = V2<T>;
     __shared__ C lds[LPW * lds_line_len<L>()];
     __shared__ C tw[2 * L];
     load_twiddles<T>(tw, twg, 2 * L, threadIdx.x, LPW * (L / E));
     __syncthreads();
-    ns_p3_tile<T, L, E, LPW, RBC>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, umax);
+    ns_p3_tile<T, L, E, LPW, RBC>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, nullptr, part);
 }
 
 // ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
@@ -281,21 +304,17 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
+    const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
     C cf[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) cf[f][i] = valid ? c3[f * FS + (long)(jt + i * TPL) * RS + j] : mk<T>(0, 0);
+        for (int i = 0; i < E; ++i) cf[f][i] = valid ? *at_bytes(c3 + f * FS + (long)(i * TPL) * RS, lo) : mk<T>(0, 0);
     }
-#pragma unroll 1
-    for (int f = 0; f < 3; ++f) {
-        C v[E];
+    // unrolled over the fields: a run-time field index into cf would put it in scratch
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = cf[f][i];
-        line_fft<T, L, E, ES>(v, lds + col, jt, tw);
-#pragma unroll
-        for (int i = 0; i < E; ++i) cf[f][i] = v[i];
-    }
+    for (int f = 0; f < 3; ++f) line_fft<T, L, E, ES>(cf[f], lds + col, jt, tw);
     if (valid) {
         const T scale = (T)(1.0 / ((double)N * N * N));
         const double h = st->h;
@@ -304,12 +323,12 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const int r = jt + i * TPL;
             if (!row_kept(r, L, K)) continue;
             const int kx = wave_k(r, N);
-            const long o = (long)r * RS + j;
+            auto at = [&](auto *b, int f) { return at_bytes(b + f * FS + (long)(i * TPL) * RS, lo); };
             C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cscale(cf[2][i], scale);
             if (add3) {
-                n0 = cadd(n0, add3[o]);
-                n1 = cadd(n1, add3[FS + o]);
-                n2 = cadd(n2, add3[2 * FS + o]);
+                n0 = cadd(n0, *at(add3, 0));
+                n1 = cadd(n1, *at(add3, 1));
+                n2 = cadd(n2, *at(add3, 2));
             }
             const T k2 = (T)(kx * kx + ky * ky + kz * kz);
             if (k2 > 0) {
@@ -324,7 +343,7 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const C nn[3] = {n0, n1, n2};
             if (mode == NS_RHS) {
 #pragma unroll
-                for (int f = 0; f < 3; ++f) out[f * FS + o] = nn[f];
+                for (int f = 0; f < 3; ++f) *at(out, f) = nn[f];
                 continue;
             }
             const double a = nu * (double)k2 * h;
@@ -333,31 +352,30 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const T th = (T)h;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const long q = f * FS + o;
-                const C uu = u[q];
+                const C uu = *at(u, f);
                 const C n = nn[f];
                 switch (mode) {
                 case RK2_S1:
-                    aux[q] = n;
-                    ust[q] = cscale(cadd(uu, cscale(n, th)), e1);
+                    *at(aux, f) = n;
+                    *at(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
                 case RK2_S2:
-                    u[q] = cadd(cscale(uu, e1), cscale(cadd(cscale(aux[q], e1), n), (T)0.5 * th));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*at(aux, f), e1), n), (T)0.5 * th));
                     break;
                 case RK4_S1:
-                    aux[q] = cscale(n, e1);
-                    ust[q] = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
+                    *at(aux, f) = cscale(n, e1);
+                    *at(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
                 case RK4_S2:
-                    aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
-                    ust[q] = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
+                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
+                    *at(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
-                    aux[q] = cadd(aux[q], cscale(n, (T)2 * e2));
-                    ust[q] = cadd(cscale(uu, e1), cscale(n, th * e2));
+                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
+                    *at(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    u[q] = cadd(cscale(uu, e1), cscale(cadd(aux[q], n), th / (T)6));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*at(aux, f), n), th / (T)6));
                     break;
                 }
             }
@@ -404,6 +422,8 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
+    const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
     C cf[3][E], nt[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) nt[i] = mk<T>(0, 0);
@@ -411,7 +431,7 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
     for (int f = 0; f < 6; ++f) {
         C v[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = valid ? c6[f * FS + (long)(jt + i * TPL) * RS + j] : mk<T>(0, 0);
+        for (int i = 0; i < E; ++i) v[i] = valid ? *at_bytes(c6 + f * FS + (long)(i * TPL) * RS, lo) : mk<T>(0, 0);
         line_fft<T, L, E, ES>(v, lds + col, jt, tw);
         if (f < 3) {
 #pragma unroll
@@ -438,8 +458,8 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
             const int r = jt + i * TPL;
             if (!row_kept(r, L, K)) continue;
             const int kx = wave_k(r, N);
-            const long o = (long)r * RS + j;
-            const C th = uin[3 * FS + o];
+            auto at = [&](auto *b, int f) { return at_bytes(b + f * FS + (long)(i * TPL) * RS, lo); };
+            const C th = *at(uin, 3);
             C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cadd(cscale(cf[2][i], scale), th);
             const T k2 = (T)(kx * kx + ky * ky + kz * kz);
             if (k2 > 0) {
@@ -451,11 +471,11 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
             } else {
                 n0 = n1 = n2 = mk<T>(0, 0);
             }
-            const C n3 = cadd(cscale(nt[i], scale), uin[2 * FS + o]);
+            const C n3 = cadd(cscale(nt[i], scale), *at(uin, 2));
             const C nn[4] = {n0, n1, n2, n3};
             if (mode == NS_RHS) {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) out[f * FS + o] = nn[f];
+                for (int f = 0; f < 4; ++f) *at(out, f) = nn[f];
                 continue;
             }
             const T eu = (T)exp(-nu_a * (double)k2 * h);
@@ -463,14 +483,13 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
             const T th_ = (T)h;
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                const long q = f * FS + o;
                 const T e = f < 3 ? eu : et;
-                const C uu = u[q];
+                const C uu = *at(u, f);
                 if (mode == RK2_S1) {
-                    aux[q] = nn[f];
-                    ust[q] = cscale(cadd(uu, cscale(nn[f], th_)), e);
+                    *at(aux, f) = nn[f];
+                    *at(ust, f) = cscale(cadd(uu, cscale(nn[f], th_)), e);
                 } else {
-                    u[q] = cadd(cscale(uu, e), cscale(cadd(cscale(aux[q], e), nn[f]), (T)0.5 * th_));
+                    *at(u, f) = cadd(cscale(uu, e), cscale(cadd(cscale(*at(aux, f), e), nn[f]), (T)0.5 * th_));
                 }
             }
         }
@@ -492,17 +511,26 @@ __global__ __launch_bounds__(W *(L / E)) void k_rbc_p5(const V2<T> *__restrict__
 }
 
 // ---- small kernels --------------------------------------------------------------------------------
-// CFL step size from the maximum P3 recorded (or the fixed step); advances t; clears umax.
-static __global__ void k_ns_set_h(NsState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// CFL step size from the maxima P3 recorded, one per workgroup (or the fixed step);
+// advances t.  One workgroup of up to 1024 threads.
+static __global__ void k_ns_set_h(NsState *st, const float *part, int nparts) {
+    __shared__ float wmax[16];
+    float m = 0.f;
+    if (part)
+        for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmaxf(m, part[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wmax[w]);
+        m = fmaxf(m, wmax[0]);
         double h = st->hfix;
         if (st->cfl_dx > 0) {
-            const double um = (double)__uint_as_float(st->umax);
+            const double um = (double)m;
             h = um > 0 ? st->cfl_dx / um : st->hfix;
         }
         st->h = h;
         st->t += h;
-        st->umax = 0u;
     }
 }
 
@@ -533,19 +561,85 @@ constexpr int ns_z_LPW(int N) {
     return TPL >= 256 ? 1 : 256 / TPL;
 }
 
+// Tile-shape variants of P1, P3 and P5 (the autotuner picks one per grid size and dtype;
+// variant 0 is the default above).  P1 / P5: a = W columns; P3: a = LPW lines.
+using NsP1Fn = void (*)(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s);
+using NsP3Fn = void (*)(void *w6, long nlines, int KZC, const void *tw, float *part, hipStream_t s);
+using NsP5Fn = void (*)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
+template <typename F> struct NsVar {
+    int a, E, v;  // v = 1: compiled for 4 waves per SIMD (at most 128 registers a thread)
+    F fn;
+};
+constexpr int NS_MAXVAR = 4;
+
 struct NsKernels {
     int N;
     tk_dtype dt;
-    void (*p1)(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s);
-    // Boussinesq variants: P1 with temperature (4 -> 7 fields), P3 (7 -> 6), P5 (6 + state of 4)
+    int np1 = 0, np3 = 0, np5 = 0;
+    NsVar<NsP1Fn> p1v[NS_MAXVAR];
+    NsVar<NsP3Fn> p3v[NS_MAXVAR];
+    NsVar<NsP5Fn> p5v[NS_MAXVAR];
+    // Boussinesq variants (default shapes): P1 with temperature (4 -> 7 fields), P3 (7 -> 6),
+    // P5 (6 + state of 4)
     void (*p1r)(const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s);
-    void (*p3r)(void *w7, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s);
+    void (*p3r)(void *w7, long nlines, int KZC, const void *tw, float *part, hipStream_t s);
     void (*p5r)(const void *c6, const void *uin, void *u, void *aux, void *ust, void *out, const NsState *st,
                 double nu_a, double kap_a, double ka, int mode, int K, int KZC, const void *tw, hipStream_t s);
-    void (*p3)(void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s);
-    void (*p5)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
 };
 const std::vector<NsKernels> &ns_kernels();
+
+template <typename T, int N, int E, int W, int WPE = 1>
+void launch_ns_p1(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
+    const long ncols = (long)(2 * K + 1) * KZC;
+    hipLaunchKernelGGL((k_ns_p1<T, N, E, W, false, WPE>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+                       (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
+}
+template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long nlines, int KZC, const void *tw,
+                                                                 float *part, hipStream_t s) {
+    hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
+                       (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, part);
+}
+template <typename T, int N, int E, int W> void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw,
+                                                             hipStream_t s) {
+    const long ncols = (long)(2 * K + 1) * KZC;
+    hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
+                       (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, (V2<T> *)a.ust, (V2<T> *)a.out, a.st,
+                       a.nu, a.mode, K, KZC, (const V2<T> *)tw);
+}
+
+// Column-pass variant (E, W) of P1 / P5 (FP32, N >= 128): kept when it differs from the
+// default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  P1 holds
+// three input fields per thread, so it only gets 512-thread variants (a 1024-thread
+// workgroup leaves 128 registers per thread); P5 gets 512 and 1024.
+template <typename T, int N, int E, int W> constexpr bool ns_x_var_ok() {
+    return sizeof(T) == 4 && N >= 128 && E <= N && N % E == 0 && rplan_ok(N, E) && W >= 1 &&
+           W * (N / E) >= 64 && W * (N / E) <= 1024 && (long)(N * (W + 1) + N) * 2 * (long)sizeof(T) <= 163840 &&
+           !(E == ns_x_E<T>(N) && W == ns_x_W<T>(N));
+}
+template <typename T, int N, int E, int W> void add_ns_p1_var(NsKernels &k) {
+    if constexpr (ns_x_var_ok<T, N, E, W>() && W * (N / E) <= 512) {
+        k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
+        // the same tile held to 128 registers, so two 512-thread workgroups share a CU
+        k.p1v[k.np1++] = {W, E, 1, &launch_ns_p1<T, N, E, W, 4>};
+    }
+}
+template <typename T, int N, int E, int W> void add_ns_p5_var(NsKernels &k) {
+    if constexpr (ns_x_var_ok<T, N, E, W>()) k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
+}
+// Line-pass variant E2 of P3 (FP32, N >= 128; L2 = N / 2 points per complex line, 256
+// threads): kept when it differs from the default and a line stays inside one wavefront.
+template <typename T, int N, int E2> constexpr bool ns_z_var_ok() {
+    constexpr int L2 = N / 2;
+    return sizeof(T) == 4 && N >= 128 && E2 >= 2 && E2 <= L2 && L2 % E2 == 0 && rplan_ok(L2, E2) &&
+           L2 / E2 <= 64 && E2 != default_E(L2);
+}
+template <typename T, int N, int E2> void add_ns_z_var(NsKernels &k) {
+    if constexpr (ns_z_var_ok<T, N, E2>()) {
+        constexpr int L2 = N / 2;
+        constexpr int LPW = 256 / (L2 / E2);
+        k.p3v[k.np3++] = {LPW, E2, 0, &launch_ns_p3<T, L2, E2, LPW>};
+    }
+}
 
 template <typename T, int N> NsKernels make_ns_kernels() {
     constexpr int E = ns_x_E<T>(N);
@@ -553,22 +647,25 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     constexpr int L2 = N / 2;
     constexpr int E2 = default_E(L2);
     constexpr int LPW = ns_z_LPW(N);
+    constexpr int Ed = default_E(N);
     NsKernels k;
     k.N = N;
     k.dt = sizeof(T) == 4 ? TK_F32 : TK_F64;
-    k.p1 = [](const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
-        const long ncols = (long)(2 * K + 1) * KZC;
-        hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
-                           (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
-    };
+    k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
+    k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
+    k.p3v[k.np3++] = {LPW, E2, 0, &launch_ns_p3<T, L2, E2, LPW>};
+    add_ns_p1_var<T, N, Ed, 512 * Ed / N>(k);
+    add_ns_p5_var<T, N, Ed, 512 * Ed / N>(k);
+    add_ns_p5_var<T, N, Ed, 1024 * Ed / N>(k);
+    add_ns_z_var<T, N, default_E(L2) / 2>(k);
     k.p1r = [](const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s) {
         const long ncols = (long)(2 * K + 1) * KZC;
         hipLaunchKernelGGL((k_ns_p1<T, N, E, W, true>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
                            (const V2<T> *)u, (V2<T> *)w7, K, KZC, (const V2<T> *)tw, (T)ka);
     };
-    k.p3r = [](void *w7, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s) {
+    k.p3r = [](void *w7, long nlines, int KZC, const void *tw, float *part, hipStream_t s) {
         hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW, true>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
-                           (V2<T> *)w7, nlines, KZC, (const V2<T> *)tw, umax);
+                           (V2<T> *)w7, nlines, KZC, (const V2<T> *)tw, part);
     };
     k.p5r = [](const void *c6, const void *uin, void *u, void *aux, void *ust, void *out, const NsState *st,
                double nu_a, double kap_a, double ka, int mode, int K, int KZC, const void *tw, hipStream_t s) {
@@ -576,16 +673,6 @@ template <typename T, int N> NsKernels make_ns_kernels() {
         hipLaunchKernelGGL((k_rbc_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
                            (const V2<T> *)c6, (const V2<T> *)uin, (V2<T> *)u, (V2<T> *)aux, (V2<T> *)ust,
                            (V2<T> *)out, st, nu_a, kap_a, (T)ka, mode, K, KZC, (const V2<T> *)tw);
-    };
-    k.p3 = [](void *w6, long nlines, int KZC, const void *tw, unsigned *umax, hipStream_t s) {
-        hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
-                           (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, umax);
-    };
-    k.p5 = [](const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
-        const long ncols = (long)(2 * K + 1) * KZC;
-        hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
-                           (const V2<T> *)a.c3, (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux,
-                           (V2<T> *)a.ust, (V2<T> *)a.out, a.st, a.nu, a.mode, K, KZC, (const V2<T> *)tw);
     };
     return k;
 }

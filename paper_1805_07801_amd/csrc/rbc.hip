@@ -62,6 +62,7 @@ struct tk_rbc_s {
     size_t fbytes = 0;
     void *w7 = nullptr, *aux = nullptr, *ust = nullptr;
     NsState *st = nullptr;
+    float *umax_part = nullptr;  // per-workgroup CFL maxima of P3 (n^2 floats)
     double *dscratch = nullptr;
     NsState hstage{};
     double nu_a = 0, kap_a = 0, ka = 1;
@@ -74,7 +75,7 @@ struct tk_rbc_s {
 static void rbc_free(tk_rbc_s *p) {
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->graph) hipGraphDestroy(p->graph);
-    void *ps[] = {p->w7, p->aux, p->ust, p->st, p->dscratch};
+    void *ps[] = {p->w7, p->aux, p->ust, p->st, p->umax_part, p->dscratch};
     for (void *q : ps)
         if (q) hipFree(q);
     delete p;
@@ -89,16 +90,17 @@ static tk_status rbc_rhs_eval(tk_rbc_s *p, const void *uin, void *u, void *out, 
     g.nk->p1r(uin, p->w7, g.K, g.KZC, g.ax.twx, p->ka, s);
     TK_TRY(launch_check("rbc P1"));
     StridedArgs y2{p->w7, p->w7, 7L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
-    g.ax.ky->fn(y2, s);
+    g.ky->fn(y2, s);
     TK_TRY(launch_check("rbc P2"));
-    g.nk->p3r(p->w7, (long)n * n, g.KZC, g.ax.twz, first_stage ? &p->st->umax : nullptr, s);
+    g.nk->p3r(p->w7, (long)n * n, g.KZC, g.ax.twz, first_stage ? p->umax_part : nullptr, s);
     TK_TRY(launch_check("rbc P3"));
     if (first_stage) {
-        hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(64), 0, s, p->st);
+        const int nparts = (int)cdiv((long)n * n, ns_z_LPW(n));
+        hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(1024), 0, s, p->st, p->umax_part, nparts);
         TK_TRY(launch_check("rbc step size"));
     }
     StridedArgs y4{p->w7, p->w7, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 0, 1.0, -1, g.K};
-    g.ax.ky->fn(y4, s);
+    g.ky->fn(y4, s);
     TK_TRY(launch_check("rbc P4"));
     g.nk->p5r(p->w7, uin, u, p->aux, p->ust, out, p->st, p->nu_a, p->kap_a, p->ka, mode, g.K, g.KZC, g.ax.twx, s);
     return launch_check("rbc P5");
@@ -133,6 +135,7 @@ extern "C" tk_status rbc_create(tk_rbc_t *out, const rbc_config *cfg) {
     NsState h0{};
     if (hipMalloc(&p->w7, 7 * p->fbytes) != hipSuccess || hipMalloc(&p->aux, 4 * p->fbytes) != hipSuccess ||
         hipMalloc(&p->ust, 4 * p->fbytes) != hipSuccess || hipMalloc((void **)&p->st, sizeof(NsState)) != hipSuccess ||
+        hipMalloc((void **)&p->umax_part, sizeof(float) * n * n) != hipSuccess ||
         hipMalloc((void **)&p->dscratch, sizeof(double) * 4 * (NS_DIAG_BLOCKS + 1)) != hipSuccess ||
         hipMemset(p->aux, 0, 4 * p->fbytes) != hipSuccess || hipMemset(p->ust, 0, 4 * p->fbytes) != hipSuccess ||
         hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {

@@ -15,7 +15,7 @@ static std::map<std::tuple<int, int, int>, TileChoice> g_tiles;
 TileChoice tuned_tile(int L, tk_dtype dt, int pass) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tiles.find(std::make_tuple(L, (int)dt, pass));
-    return it == g_tiles.end() ? TileChoice{0, 0} : it->second;
+    return it == g_tiles.end() ? TileChoice{0, 0, 0} : it->second;
 }
 
 void set_tuned_tile(int L, tk_dtype dt, int pass, TileChoice c) {
@@ -43,6 +43,7 @@ void clear_tuned_tiles() {
 #include <vector>
 
 #include "fft_api.hpp"
+#include "ns_api.hpp"
 #include "reduce.hpp"
 
 namespace tk {
@@ -62,17 +63,19 @@ static tk_status time_it(const std::function<void()> &f, int iters, hipStream_t 
     TK_HIP_CHECK(hipEventCreate(&e1));
     std::vector<float> t;
     f();  // warm-up
-    for (int i = 0; i < iters; ++i) {
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < iters && err == hipSuccess; ++i) {
         hipEventRecord(e0, s);
         f();
         hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+        err = hipEventSynchronize(e1);
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
         t.push_back(ms);
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(TK_EHIP, "autotune timing: %s", hipGetErrorString(err));
     std::sort(t.begin(), t.end());
     *ms_out = t[t.size() / 2];
     return launch_check("autotune candidate");
@@ -123,7 +126,7 @@ extern "C" tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype 
         else run_s(pass == 1 ? ax.ky : ax.kx, B.ref);
         TK_TRY(launch_check("autotune reference"));
         float best_ms = 1e30f;
-        TileChoice best{0, 0};
+        TileChoice best{0, 0, 0};
         if (pass == 0) {
             for (const auto &k : z_kernels()) {
                 if (k.N != L || k.dt != dt) continue;
@@ -137,7 +140,7 @@ extern "C" tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype 
                 rep += line;
                 if (ok && ms < best_ms) {
                     best_ms = ms;
-                    best = {k.nt, k.E};
+                    best = {k.nt, k.E, 0};
                 }
             }
         } else {
@@ -148,17 +151,18 @@ extern "C" tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype 
                 double num, den;
                 TK_TRY(reduce_diff(B.b, B.ref, nout, dt, &num, &den, s));
                 const bool ok = std::sqrt(num / den) <= tol;
-                snprintf(line, sizeof(line), "pass %c L=%d W=%d E=%d nt=%d lds=%d: %.4f ms %s\n", pass == 1 ? 'y' : 'x',
-                         L, k.W, k.E, k.nt, k.lds, ms, ok ? "ok" : "REJECTED");
+                snprintf(line, sizeof(line), "pass %c L=%d W=%d E=%d v=%d nt=%d lds=%d: %.4f ms %s\n",
+                         pass == 1 ? 'y' : 'x', L, k.W, k.E, k.var, k.nt, k.lds, ms, ok ? "ok" : "REJECTED");
                 rep += line;
                 if (ok && ms < best_ms) {
                     best_ms = ms;
-                    best = {k.W, k.E};
+                    best = {k.W, k.E, k.var};
                 }
             }
         }
         if (best.a > 0) set_tuned_tile(L, dt, pass, best);
-        snprintf(line, sizeof(line), "chosen pass %d L=%d: a=%d E=%d (%.4f ms)\n", pass, L, best.a, best.E, best_ms);
+        snprintf(line, sizeof(line), "chosen pass %d L=%d: a=%d E=%d v=%d (%.4f ms)\n", pass, L, best.a, best.E, best.v,
+                 best_ms);
         rep += line;
     }
     if (report && report_len > 0) {
@@ -168,20 +172,41 @@ extern "C" tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype 
     return TK_OK;
 }
 
-extern "C" tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E) {
-    if (pass < 0 || pass > 2) return fail(TK_EINVAL, "pass must be 0, 1 or 2");
+// Solver passes in the tile table: 3 = P1, 4 = P3, 5 = P5 of the grid size L.
+static const NsKernels *ns_kernels_of(int n, tk_dtype dt) {
+    for (const auto &k : ns_kernels())
+        if (k.N == n && k.dt == dt) return &k;
+    return nullptr;
+}
+
+template <typename V> static int ns_var_index(const V *v, int nv, int a, int E, int var) {
+    for (int i = 0; i < nv; ++i)
+        if (v[i].a == a && v[i].E == E && v[i].v == var) return i;
+    return -1;
+}
+
+extern "C" tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant) {
+    if (pass < 0 || pass > 6) return fail(TK_EINVAL, "pass must be 0..6");
     if (a <= 0) {
-        set_tuned_tile(L, dt, pass, {0, 0});
+        set_tuned_tile(L, dt, pass, {0, 0, 0});
         return TK_OK;
     }
     bool found = false;
-    if (pass == 0) {
-        for (const auto &k : z_kernels()) found |= (k.N == L && k.dt == dt && k.nt == a && k.E == E);
+    if (pass >= 3 && pass <= 5) {
+        const NsKernels *k = ns_kernels_of(L, dt);
+        if (k) {
+            if (pass == 3) found = ns_var_index(k->p1v, k->np1, a, E, variant) >= 0;
+            else if (pass == 4) found = ns_var_index(k->p3v, k->np3, a, E, variant) >= 0;
+            else found = ns_var_index(k->p5v, k->np5, a, E, variant) >= 0;
+        }
+    } else if (pass == 0) {
+        for (const auto &k : z_kernels()) found |= (k.N == L && k.dt == dt && k.nt == a && k.E == E && variant == 0);
     } else {
-        for (const auto &k : strided_kernels()) found |= (k.L == L && k.dt == dt && k.W == a && k.E == E);
+        for (const auto &k : strided_kernels())
+            found |= (k.L == L && k.dt == dt && k.W == a && k.E == E && k.var == variant);
     }
-    if (!found) return fail(TK_EUNSUPPORTED, "no compiled tile L=%d pass=%d a=%d E=%d", L, pass, a, E);
-    set_tuned_tile(L, dt, pass, {a, E});
+    if (!found) return fail(TK_EUNSUPPORTED, "no compiled tile L=%d pass=%d a=%d E=%d v=%d", L, pass, a, E, variant);
+    set_tuned_tile(L, dt, pass, {a, E, variant});
     return TK_OK;
 }
 
@@ -190,26 +215,192 @@ extern "C" tk_status fft3d_tune_clear(void) {
     return TK_OK;
 }
 
-extern "C" int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int cap) {
+extern "C" int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int *v, int cap) {
     int n = 0;
+    if (pass >= 3 && pass <= 5) {
+        const NsKernels *k = ns_kernels_of(L, dt);
+        if (!k) return 0;
+        const int nv = pass == 3 ? k->np1 : pass == 4 ? k->np3 : k->np5;
+        for (int i = 0; i < nv; ++i) {
+            if (i < cap) {
+                const int ai = pass == 3 ? k->p1v[i].a : pass == 4 ? k->p3v[i].a : k->p5v[i].a;
+                const int Ei = pass == 3 ? k->p1v[i].E : pass == 4 ? k->p3v[i].E : k->p5v[i].E;
+                const int vi = pass == 3 ? k->p1v[i].v : pass == 4 ? k->p3v[i].v : k->p5v[i].v;
+                if (a) a[i] = ai;
+                if (E) E[i] = Ei;
+                if (v) v[i] = vi;
+            }
+        }
+        return nv;
+    }
     if (pass == 0) {
         for (const auto &k : z_kernels())
             if (k.N == L && k.dt == dt) {
-                if (n < cap && a && E) {
-                    a[n] = k.nt;
-                    E[n] = k.E;
+                if (n < cap) {
+                    if (a) a[n] = k.nt;
+                    if (E) E[n] = k.E;
+                    if (v) v[n] = 0;
                 }
                 ++n;
             }
     } else {
         for (const auto &k : strided_kernels())
             if (k.L == L && k.dt == dt) {
-                if (n < cap && a && E) {
-                    a[n] = k.W;
-                    E[n] = k.E;
+                if (n < cap) {
+                    if (a) a[n] = k.W;
+                    if (E) E[n] = k.E;
+                    if (v) v[n] = k.var;
                 }
                 ++n;
             }
     }
     return n;
 }
+
+// ---- solver passes ---------------------------------------------------------------------------------
+// Each variant of P1, P3 and P5 of an n^3 grid runs on the same pseudo-random fields; it is
+// admitted when its output matches variant 0's to the transform tolerance, timed like the
+// FFT candidates, and the fastest admitted one goes into the tile table (passes 3, 4, 5).
+struct NsTuneBufs {
+    void *u = nullptr, *w6 = nullptr, *in6 = nullptr, *ref = nullptr, *out = nullptr;
+    NsState *st = nullptr;
+    ~NsTuneBufs() {
+        for (void *p : {u, w6, in6, ref, out, (void *)st})
+            if (p) hipFree(p);
+    }
+};
+
+extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, int report_len) {
+    if (iters < 1) return fail(TK_EINVAL, "iters must be >= 1");
+    NsGrid g;
+    TK_TRY(ns_grid_init(&g, n, dt));
+    const NsKernels *k = g.nk;
+    const long nf = (long)n * n * (n / 2 + 1);          // complex values per field
+    const size_t fb = nf * 2 * (dt == TK_F32 ? 4 : 8);  // bytes per field
+    NsTuneBufs B;
+    TK_HIP_CHECK(hipMalloc(&B.u, 3 * fb));
+    TK_HIP_CHECK(hipMalloc(&B.w6, 6 * fb));
+    TK_HIP_CHECK(hipMalloc(&B.in6, 6 * fb));
+    TK_HIP_CHECK(hipMalloc(&B.ref, 6 * fb));
+    TK_HIP_CHECK(hipMalloc(&B.out, 3 * fb));
+    TK_HIP_CHECK(hipMalloc(&B.st, sizeof(NsState)));
+    hipStream_t s = nullptr;
+    TK_HIP_CHECK(hipMemset(B.st, 0, sizeof(NsState)));
+    TK_TRY(fill_pattern(B.u, 6 * nf, dt, 77u, s));
+    TK_TRY(fill_pattern(B.in6, 12 * nf, dt, 78u, s));
+    const double tol = dt == TK_F32 ? 1e-5 : 1e-12;
+    std::string rep;
+    char line[256];
+    auto finish = [&](int pass, int a, int E, int v, float ms) {
+        if (a > 0) set_tuned_tile(n, dt, pass, {a, E, v});
+        snprintf(line, sizeof(line), "chosen pass %d L=%d: a=%d E=%d v=%d (%.4f ms)\n", pass, n, a, E, v, ms);
+        rep += line;
+    };
+    auto check = [&](const void *x, const void *r, long nreal, bool *ok) -> tk_status {
+        double num, den;
+        TK_TRY(reduce_diff(x, r, nreal, dt, &num, &den, s));
+        *ok = den > 0 && std::sqrt(num / den) <= tol;
+        return TK_OK;
+    };
+    // P1: u (3 fields) -> w6
+    {
+        float best = 1e30f;
+        int ba = 0, bE = 0, bv = 0;
+        for (int i = 0; i < k->np1; ++i) {
+            const auto &v = k->p1v[i];
+            TK_HIP_CHECK(hipMemsetAsync(B.w6, 0, 6 * fb, s));
+            v.fn(B.u, B.w6, g.K, g.KZC, g.ax.twx, s);
+            TK_TRY(launch_check("autotune P1"));
+            if (i == 0) TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.w6, 6 * fb, hipMemcpyDeviceToDevice, s));
+            bool ok = true;
+            if (i > 0) TK_TRY(check(B.w6, B.ref, 12 * nf, &ok));
+            float ms;
+            TK_TRY(time_it([&] { v.fn(B.u, B.w6, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p1 N=%d W=%d E=%d v=%d: %.4f ms %s\n", n, v.a, v.E, v.v, ms,
+                     ok ? "ok" : "REJECTED");
+            rep += line;
+            if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
+        }
+        finish(3, ba, bE, bv, best);
+    }
+    // P3: in place on 6 fields (restored from in6 before the checked run)
+    {
+        float best = 1e30f;
+        int ba = 0, bE = 0, bv = 0;
+        for (int i = 0; i < k->np3; ++i) {
+            const auto &v = k->p3v[i];
+            TK_HIP_CHECK(hipMemcpyAsync(B.w6, B.in6, 6 * fb, hipMemcpyDeviceToDevice, s));
+            v.fn(B.w6, (long)n * n, g.KZC, g.ax.twz, nullptr, s);
+            TK_TRY(launch_check("autotune P3"));
+            if (i == 0) TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.w6, 3 * fb, hipMemcpyDeviceToDevice, s));
+            bool ok = true;
+            if (i > 0) TK_TRY(check(B.w6, B.ref, 6 * nf, &ok));
+            float ms;
+            TK_TRY(time_it([&] { v.fn(B.w6, (long)n * n, g.KZC, g.ax.twz, nullptr, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p3 N=%d LPW=%d E=%d: %.4f ms %s\n", n, v.a, v.E, ms,
+                     ok ? "ok" : "REJECTED");
+            rep += line;
+            if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
+        }
+        finish(4, ba, bE, bv, best);
+    }
+    // P2 (the Y pass with the solver's row masks and kept columns), in place on 6 fields;
+    // candidates are all strided tiles of length n
+    {
+        const long nzh = n / 2 + 1;
+        StridedArgs y2{B.w6, B.w6, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
+        float best = 1e30f;
+        int ba = 0, bE = 0, bv = 0;
+        bool first = true;
+        for (const auto &v : strided_kernels()) {
+            if (v.L != n || v.dt != dt) continue;
+            TK_HIP_CHECK(hipMemcpyAsync(B.w6, B.in6, 6 * fb, hipMemcpyDeviceToDevice, s));
+            v.fn(y2, s);
+            snprintf(line, sizeof(line), "autotune P2 W=%d E=%d v=%d", v.W, v.E, v.var);
+            TK_TRY(launch_check(line));
+            if (first) TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.w6, 6 * fb, hipMemcpyDeviceToDevice, s));
+            bool ok = true;
+            if (!first) TK_TRY(check(B.w6, B.ref, 12 * nf, &ok));
+            first = false;
+            float ms;
+            TK_TRY(time_it([&] { v.fn(y2, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p2 N=%d W=%d E=%d v=%d: %.4f ms %s\n", n, v.W, v.E, v.var, ms,
+                     ok ? "ok" : "REJECTED");
+            rep += line;
+            if (ok && ms < best) best = ms, ba = v.W, bE = v.E, bv = v.var;
+        }
+        finish(6, ba, bE, bv, best);
+    }
+    // P5 (right-hand-side mode): 3 fields of in6 -> out
+    {
+        float best = 1e30f;
+        int ba = 0, bE = 0, bv = 0;
+        P5Args a{};
+        a.c3 = B.in6;
+        a.out = B.out;
+        a.st = B.st;
+        a.mode = NS_RHS;
+        for (int i = 0; i < k->np5; ++i) {
+            const auto &v = k->p5v[i];
+            TK_HIP_CHECK(hipMemsetAsync(B.out, 0, 3 * fb, s));
+            v.fn(a, g.K, g.KZC, g.ax.twx, s);
+            TK_TRY(launch_check("autotune P5"));
+            if (i == 0) TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.out, 3 * fb, hipMemcpyDeviceToDevice, s));
+            bool ok = true;
+            if (i > 0) TK_TRY(check(B.out, B.ref, 6 * nf, &ok));
+            float ms;
+            TK_TRY(time_it([&] { v.fn(a, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p5 N=%d W=%d E=%d: %.4f ms %s\n", n, v.a, v.E, ms, ok ? "ok" : "REJECTED");
+            rep += line;
+            if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
+        }
+        finish(5, ba, bE, bv, best);
+    }
+    TK_HIP_CHECK(hipStreamSynchronize(s));
+    if (report && report_len > 0) {
+        strncpy(report, rep.c_str(), report_len - 1);
+        report[report_len - 1] = 0;
+    }
+    return TK_OK;
+}
+

@@ -6,9 +6,11 @@
 namespace tk {
 
 // Strided passes (pass 1 = Y, 2 = X): a = column width W; Z pass (pass 0): a = threads
-// per workgroup.  E = points per thread.  a = 0 means no entry.
+// per workgroup.  E = points per thread; v = kernel variant of a strided pass (0: one
+// tile per workgroup, 1: persistent with loads issued one tile ahead).  a = 0 means no
+// entry.
 struct TileChoice {
-    int a, E;
+    int a, E, v;
 };
 
 TileChoice tuned_tile(int L, tk_dtype dt, int pass);

@@ -105,15 +105,43 @@ def test_every_tile_candidate_matches_oracle(tk, n):
             shape = shapes[p]
             f = synth.gaussian_field((1,) + shape, n + p)
             ref = offt.rfft3(f[0].astype(np.float64))
-            for (a, E) in tk.tile_candidates(n, torch.float32, p):
-                tk.tune_set(n, torch.float32, p, a, E)
+            for (a, E, v) in tk.tile_candidates(n, torch.float32, p):
+                tk.tune_set(n, torch.float32, p, a, E, v)
                 plan = tk.FFT3D(*shape, dtype=torch.float32)
                 assert f"E={E}" in plan.describe(p)
                 X = plan.r2c(torch.from_numpy(f).cuda())
-                assert diag.rel_l2(X.cpu().numpy()[0], ref, shape[2]) <= TOL["f32"], (p, a, E)
+                assert diag.rel_l2(X.cpu().numpy()[0], ref, shape[2]) <= TOL["f32"], (p, a, E, v)
                 back = plan.c2r(X).cpu().numpy()
-                assert diag.rel_l2(back, f) <= TOL["f32"], (p, a, E)
+                assert diag.rel_l2(back, f) <= TOL["f32"], (p, a, E, v)
                 plan.close()
             tk.tune_set(n, torch.float32, p, 0, 0)
     finally:
         tk.tune_clear()
+
+
+@pytest.mark.parametrize("L", [256, 512])
+def test_persistent_candidates_full_rounds_and_tail(tk, L):
+    """The persistent strided variants (all three tile orders) at sizes where every
+    workgroup takes several full tiles and the leftover columns are cut into narrow tail
+    tiles (ncols = 256 * 65)."""
+    import torch
+    try:
+        for p, shape in ((1, (256, L, 128)), (2, (L, 256, 128))):
+            f = synth.gaussian_field((1,) + shape, 7 + p)
+            ref = offt.rfft3(f[0].astype(np.float64))
+            cands = [c for c in tk.tile_candidates(L, torch.float32, p) if c[2] >= 1]
+            assert cands, "no persistent candidate compiled for L=%d" % L
+            x = torch.from_numpy(f).cuda()
+            for (a, E, v) in cands:
+                tk.tune_set(L, torch.float32, p, a, E, v)
+                plan = tk.FFT3D(*shape, dtype=torch.float32)
+                assert "v=%d" % v in plan.describe(p)
+                X = plan.r2c(x)
+                assert diag.rel_l2(X.cpu().numpy()[0], ref, shape[2]) <= TOL["f32"], (p, a, E)
+                back = plan.c2r(X).cpu().numpy()
+                assert diag.rel_l2(back, f) <= TOL["f32"], (p, a, E)
+                plan.close()
+            tk.tune_set(L, torch.float32, p, 0, 0)
+    finally:
+        tk.tune_clear()
+

@@ -39,6 +39,31 @@ def test_rhs_vs_oracle(tk, n, dt):
     assert np.max(np.abs(got * ~ons.dealias_mask(n))) == 0
 
 
+@pytest.mark.parametrize("n", [128, 192, 256])
+def test_rhs_every_solver_variant_vs_oracle(tk, n):
+    """Every compiled tile variant of P1, P3, P5 and of the solver's Y passes (the
+    autotuner's choices) reproduces the oracle's right-hand side; the masked modes stay
+    exactly zero."""
+    import torch
+    u = rand_state(n, seed=n + 1)
+    ref = ons.rhs(u)
+    ud = to_gpu(u, "f32")
+    try:
+        for p in (3, 4, 5, 6):
+            cands = tk.tile_candidates(n, torch.float32, p)
+            assert cands, (n, p)
+            for (a, E, v) in cands:
+                tk.tune_set(n, torch.float32, p, a, E, v)
+                s = tk.NS(n, dtype=torch.float32, nu=0.0)
+                got = s.rhs(ud).cpu().numpy()
+                s.close()
+                assert diag.rel_l2(got, ref, n) <= 1e-5, (p, a, E)
+                assert np.max(np.abs(got * ~ons.dealias_mask(n))) == 0, (p, a, E)
+            tk.tune_set(n, torch.float32, p, 0, 0)
+    finally:
+        tk.tune_clear()
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_taylor_green_32_ten_steps(tk, dt):
     """32^3 Taylor-Green, nu = 0.01, dt = 0.01, IF-RK2, 10 steps."""
