@@ -142,7 +142,8 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
  * 2 = X (a = columns per tile); E = points per thread; variant (strided passes; 0 for Z)
  * 0 = one tile per workgroup, 1..3 = persistent workgroups that issue the next tile's loads
  * before transforming the current one (1: tiles dealt round-robin, 2: round-robin with a
- * contiguous run per XCD, 3: consecutive tiles per workgroup).  Passes 3, 4, 5 are the
+ * contiguous run per XCD, 3: consecutive tiles per workgroup), 4 = one tile per workgroup
+ * with each XCD sweeping its own eighth of the tiles.  Passes 3, 4, 5 are the
  * solver passes P1 (a = columns), P3 (a = lines per workgroup) and P5 (a = columns) of an
  * L^3 grid (variant 1: the tile compiled for two workgroups per CU), pass 6 the solver's
  * Y passes P2 / P4 (a strided tile as for pass 1); solver handles created afterwards use

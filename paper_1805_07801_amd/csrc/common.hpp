@@ -88,6 +88,18 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
     return (b & 7u) * per + (b >> 3);
 }
 
+// Tile of block b of nb for a pass that sweeps its data once from one end to the other
+// (from the far end when rev): blocks are dealt to the 8 XCDs in turn, and inside each
+// window of 64 blocks an XCD takes 8 consecutive tiles (neighbours share the cache lines
+// at their boundaries); windows follow each other in order.  A pass that starts where
+// the previous pass ended finds that pass's last writes still in the memory-side cache.
+// The partial last window keeps the identity.
+__device__ __forceinline__ unsigned sweep_tile(unsigned b, unsigned nb, int rev) {
+    const unsigned full = nb & ~63u;
+    const unsigned t = b >= full ? b : (b & ~63u) | ((b & 7u) << 3) | ((b >> 3) & 7u);
+    return rev ? nb - 1 - t : t;
+}
+
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace tk

@@ -49,20 +49,21 @@ const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E) {
 // touches and TPL rows of SI.  When that exceeds 32 bits (several 1024^3 members in one
 // call) the pass is launched once per plane, where a tile never crosses a plane.
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
-                       long SI, const void *tw, int inv, double scale, hipStream_t s) {
+                       long SI, const void *tw, int inv, double scale, hipStream_t s, int rev) {
     const long esz = k->dt == TK_F32 ? 8 : 16;
     const long in_plane = (CB + (long)(k->L / k->E) * SI) * esz;
     const long crossing = ((k->W + CB - 2) / CB) * SO * esz;
     const long lim = 1L << 32;
     if (in_plane + crossing < lim) {
-        StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale, -1, -1};
+        StridedArgs a{src, dst, ncols, CB, SO, SI, tw, inv, scale, -1, -1, rev};
         k->fn(a, s);
         return launch_check("strided pass");
     }
     if (in_plane >= lim) return fail(TK_EUNSUPPORTED, "strided pass: a plane spans more than 4 GB");
     for (long p = 0; p < ncols / CB; ++p) {
-        StridedArgs a{(const char *)src + p * SO * esz, (char *)dst + p * SO * esz, CB, CB, SO, SI, tw, inv, scale,
-                      -1, -1};
+        const long q = rev ? ncols / CB - 1 - p : p;
+        StridedArgs a{(const char *)src + q * SO * esz, (char *)dst + q * SO * esz, CB, CB, SO, SI, tw, inv, scale,
+                      -1, -1, rev};
         k->fn(a, s);
     }
     return launch_check("strided pass");
@@ -77,22 +78,23 @@ static tk_status r2r_pass(const R2RKernel *k, int basis, const void *src, void *
     return launch_check("sine/cosine pass");
 }
 
-tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s) {
+tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s, int rev) {
     const long nzh = ax.nz / 2 + 1;
     if (ax.by != 0)
         return r2r_pass(ax.ry, ax.by, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, ax.twqy,
                         inv, 1.0, s);
-    return strided_pass(ax.ky, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, inv, 1.0, s);
+    return strided_pass(ax.ky, src, dst, nfields * ax.nx * nzh, nzh, (long)ax.ny * nzh, nzh, ax.twy, inv, 1.0, s,
+                        rev);
 }
 
 tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, double scale,
-                     hipStream_t s) {
+                     hipStream_t s, int rev) {
     const long nzh = ax.nz / 2 + 1;
     const long cb = (long)ax.ny * nzh;
     if (ax.bx != 0)
         return r2r_pass(ax.rx, ax.bx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, ax.twqx, inv, scale,
                         s);
-    return strided_pass(ax.kx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, inv, scale, s);
+    return strided_pass(ax.kx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, inv, scale, s, rev);
 }
 
 tk_status axes_set_basis(FftAxes *ax, int bx, int by) {
@@ -121,14 +123,15 @@ tk_status axes_set_basis(FftAxes *ax, int bx, int by) {
     return TK_OK;
 }
 
-tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s) {
-    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, scale};
+tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s,
+                    int rev) {
+    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, scale, rev};
     ax.kz->r2c(a, s);
     return launch_check("z r2c pass");
 }
 
-tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s) {
-    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, 1.0};
+tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s, int rev) {
+    ZArgs a{src, dst, nfields * ax.nx * ax.ny, ax.twz, 1.0, rev};
     ax.kz->c2r(a, s);
     return launch_check("z c2r pass");
 }
@@ -253,9 +256,11 @@ extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out
     const double scale = 1.0 / ((double)ax.nx * ax.ny * ax.nz);
     hipEvent_t *ev = p->timing ? &p->ev[(p->nr2c % NSET) * 8] : nullptr;
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[0], s));
+    // sweep directions: each pass starts where the previous one ended (its last writes are
+    // still in the memory-side cache) when the two visit the data in the same order
     TK_TRY(fft_z_r2c(ax, real_in, cplx_out, p->batch, 1.0, s));
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[1], s));
-    TK_TRY(fft_y_pass(ax, cplx_out, cplx_out, p->batch, 0, s));
+    TK_TRY(fft_y_pass(ax, cplx_out, cplx_out, p->batch, 0, s, 1));
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[2], s));
     TK_TRY(fft_x_pass(ax, cplx_out, cplx_out, p->batch, 0, scale, s));
     if (ev) {
@@ -284,12 +289,14 @@ extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out
         if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
         TK_TRY(fft_x_pass(ax, p->ws, p->ws, p->batch, 1, 1.0, s));
     } else {
-        TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s));
+        // X backwards over the columns the forward X pass wrote last, then Z backwards over
+        // the x planes the Y pass wrote last
+        TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s, 1));
         if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
         TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
     }
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
-    TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s));
+    TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s, (p->flags & TK_FFT_C2R_Y_FIRST) ? 0 : 1));
     if (ev) {
         TK_HIP_CHECK(hipEventRecord(ev[7], s));
         p->nc2r++;

@@ -25,13 +25,16 @@ tk_status axes_set_basis(FftAxes *ax, int bx, int by);
 const StridedKernel *pick_strided(int L, tk_dtype dt, int want_W, int want_E, int want_v);
 const ZKernel *pick_z(int N, tk_dtype dt, int want_nt, int want_E);
 tk_status strided_pass(const StridedKernel *k, const void *src, void *dst, long ncols, long CB, long SO,
-                       long SI, const void *tw, int inv, double scale, hipStream_t s);
+                       long SI, const void *tw, int inv, double scale, hipStream_t s, int rev = 0);
 
-// Passes over `nfields` consecutive spectral fields [nfields][nx][ny][nz/2+1].
-tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s);
+// Passes over `nfields` consecutive spectral fields [nfields][nx][ny][nz/2+1].  rev: sweep
+// the data from the far end, to start where the previous pass ended (see sweep_tile).
+tk_status fft_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s,
+                     int rev = 0);
 tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, double scale,
-                     hipStream_t s);
-tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s);
-tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s);
+                     hipStream_t s, int rev = 0);
+tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s,
+                    int rev = 0);
+tk_status fft_z_c2r(const FftAxes &ax, const void *src, void *dst, long nfields, hipStream_t s, int rev = 0);
 
 }  // namespace tk

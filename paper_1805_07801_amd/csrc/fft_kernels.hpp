@@ -29,11 +29,13 @@ struct StridedArgs {
     // min(r, L - r) <= kl are read (the others are taken as zero); with ks >= 0 only such
     // rows are written.  -1: every row.
     int kl = -1, ks = -1;
+    int rev = 0;  // sweep the columns from the last one (see sweep_tile)
 };
 using StridedFn = void (*)(const StridedArgs &, hipStream_t);
 
-// var 0: one tile per workgroup; var 1..3: persistent workgroups with the next tile's loads
-// issued ahead (k_strided_pp), tile order var.
+// var 0: one tile per workgroup, one sweep over the tiles; var 1..3: persistent workgroups
+// with the next tile's loads issued ahead (k_strided_pp), tile order var; var 4: one tile
+// per workgroup, each XCD sweeping its own eighth of the tiles.
 struct StridedKernel {
     int L;
     tk_dtype dt;
@@ -48,6 +50,7 @@ struct ZArgs {
     long nlines;
     const void *tw;  // W_N^j table, N = real line length
     double scale;    // r2c only
+    int rev = 0;     // sweep the lines from the last one (see sweep_tile)
 };
 using ZFn = void (*)(const ZArgs &, hipStream_t);
 
@@ -182,30 +185,34 @@ template <typename T, int L, int E, int W> constexpr int strided_lds_elems() { r
 template <typename T, int L, int E, int W, bool MASK>
 __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                          long SO, long SI, const V2<T> *__restrict__ twg,
-                                                         int inv, T scale, int kl, int ks) {
+                                                         int inv, T scale, int kl, int ks, int rev,
+                                                         int regions) {
     using C = V2<T>;
     constexpr int NT = W * (L / E);
     __shared__ C lds[strided_lds_elems<T, L, E, W>()];
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, NT);
     __syncthreads();
-    strided_tile<T, L, E, W, MASK>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks,
-                                   xcd_tile(blockIdx.x, gridDim.x), lds, tw);
+    // regions: each XCD sweeps its own eighth of the tiles (the 8 sweeps run side by side)
+    unsigned t = regions ? xcd_tile(blockIdx.x, gridDim.x) : sweep_tile(blockIdx.x, gridDim.x, 0);
+    if (rev) t = gridDim.x - 1 - t;
+    strided_tile<T, L, E, W, MASK>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks, t, lds, tw);
 }
 
 // Row masks select the MASK instantiation; plain transforms run the branch-free one.
-template <typename T, int L, int E, int W>
+// REGIONS: tile order by XCD regions instead of one sweep (variant 4).
+template <typename T, int L, int E, int W, int REGIONS = 0>
 void launch_strided(const StridedArgs &a, hipStream_t s) {
     constexpr int NT = W * (L / E);
     unsigned nb = cdiv(a.ncols, W);
     if (a.kl >= 0 || a.ks >= 0)
         hipLaunchKernelGGL((k_strided<T, L, E, W, true>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
                            (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
-                           a.ks);
+                           a.ks, a.rev, REGIONS);
     else
         hipLaunchKernelGGL((k_strided<T, L, E, W, false>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
                            (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
-                           a.ks);
+                           a.ks, a.rev, REGIONS);
 }
 
 // ---- persistent strided pass ----------------------------------------------------------------------
@@ -226,7 +233,7 @@ template <typename T, int L, int E, int W, bool MASK>
 __global__ __launch_bounds__(W *(L / E)) void k_strided_pp(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                             long SO, long SI, const V2<T> *__restrict__ twg,
                                                             int inv, T scale, int kl, int ks, long q, int wt,
-                                                            int ntail, int order) {
+                                                            int ntail, int order, int rev) {
     using C = V2<T>;
     constexpr int NT = W * (L / E);
     constexpr int ES = strided_es<L, E, W>();
@@ -236,21 +243,25 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided_pp(const V2<T> *src, V2<
     __syncthreads();
     const long G = gridDim.x;
     const long g = (order == 2 && (G & 7) == 0) ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-    const long nu = q + (g < ntail ? 1 : 0);
-    auto addr_of = [&](long k) {
+    const bool has_tail = g < ntail;
+    const long nu = q + (has_tail ? 1 : 0);
+    // unit u -> round (q = the tail); rev runs the tail first, then the rounds backwards
+    auto round_of = [&](long u) { return !rev ? u : (has_tail ? (u == 0 ? q : q - u) : q - 1 - u); };
+    auto addr_of = [&](long u) {
+        const long k = round_of(u);
         return k < q ? tile_addr<T, W>((order == 3 ? g * q + k : k * G + g) * W, W, ncols, CB, SO, SI)
                      : tile_addr<T, W>(q * G * W + g * wt, wt, ncols, CB, SO, SI);
     };
     C nx[E];
     TileAddr an = addr_of(0);
     if (nu > 0) strided_load<T, L, E, W, MASK>(nx, src, an, SI, kl);
-    for (long k = 0; k < nu; ++k) {
+    for (long u = 0; u < nu; ++u) {
         const TileAddr a = an;
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = nx[i];
-        if (k + 1 < nu) {
-            an = addr_of(k + 1);
+        if (u + 1 < nu) {
+            an = addr_of(u + 1);
             strided_load<T, L, E, W, MASK>(nx, src, an, SI, kl);
         }
         if (inv) {
@@ -284,11 +295,11 @@ void launch_strided_pp(const StridedArgs &a, hipStream_t s) {
     if (mask)
         hipLaunchKernelGGL((k_strided_pp<T, L, E, W, true>), dim3((unsigned)G), dim3(NT), 0, s, (const V2<T> *)a.src,
                            (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
-                           a.ks, q, wt, ntail, ORDER);
+                           a.ks, q, wt, ntail, ORDER, a.rev);
     else
         hipLaunchKernelGGL((k_strided_pp<T, L, E, W, false>), dim3((unsigned)G), dim3(NT), 0, s,
                            (const V2<T> *)a.src, (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw,
-                           a.inv, (T)a.scale, a.kl, a.ks, q, wt, ntail, ORDER);
+                           a.inv, (T)a.scale, a.kl, a.ks, q, wt, ntail, ORDER, a.rev);
 }
 
 // ---- Z pass: real lines <-> half spectra ----------------------------------------------------------
@@ -301,7 +312,8 @@ void launch_strided_pp(const StridedArgs &a, hipStream_t s) {
 //             done as conj(DFT(conj Z')); x[2n] = Re z[n], x[2n+1] = Im z[n].
 template <typename T, int L, int E, int LPW>
 __global__ __launch_bounds__(LPW *(L / E)) void k_z_r2c(const T *__restrict__ src, V2<T> *__restrict__ dst,
-                                                         long nlines, const V2<T> *__restrict__ twg, T scale) {
+                                                         long nlines, const V2<T> *__restrict__ twg, T scale,
+                                                         int rev) {
     using C = V2<T>;
     constexpr int TPL = L / E;
     constexpr int NT = LPW * TPL;
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_z_r2c(const T *__restrict__ sr
     const int tid = threadIdx.x;
     const int ln = tid / TPL;
     const int jt = tid % TPL;
-    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const long l = (long)sweep_tile(blockIdx.x, gridDim.x, rev) * LPW + ln;
     const bool valid = l < nlines;
     const C *s2 = reinterpret_cast<const C *>(src) + l * L;
     C v[E];
@@ -343,7 +355,7 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_z_r2c(const T *__restrict__ sr
 
 template <typename T, int L, int E, int LPW>
 __global__ __launch_bounds__(LPW *(L / E)) void k_z_c2r(const V2<T> *__restrict__ src, T *__restrict__ dst,
-                                                         long nlines, const V2<T> *__restrict__ twg) {
+                                                         long nlines, const V2<T> *__restrict__ twg, int rev) {
     using C = V2<T>;
     constexpr int TPL = L / E;
     constexpr int NT = LPW * TPL;
@@ -354,7 +366,7 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_z_c2r(const V2<T> *__restrict_
     const int tid = threadIdx.x;
     const int ln = tid / TPL;
     const int jt = tid % TPL;
-    const long l = (long)xcd_tile(blockIdx.x, gridDim.x) * LPW + ln;
+    const long l = (long)sweep_tile(blockIdx.x, gridDim.x, rev) * LPW + ln;
     const bool valid = l < nlines;
     const C *s = src + (valid ? l : 0) * NZH;
     C v[E], xm[E];
@@ -391,7 +403,7 @@ void launch_z_r2c(const ZArgs &a, hipStream_t s) {
     constexpr int NT = LPW * (L / E);
     unsigned nb = cdiv(a.nlines, LPW);
     hipLaunchKernelGGL((k_z_r2c<T, L, E, LPW>), dim3(nb), dim3(NT), 0, s, (const T *)a.src, (V2<T> *)a.dst,
-                       a.nlines, (const V2<T> *)a.tw, (T)a.scale);
+                       a.nlines, (const V2<T> *)a.tw, (T)a.scale, a.rev);
 }
 
 template <typename T, int L, int E, int LPW>
@@ -399,7 +411,7 @@ void launch_z_c2r(const ZArgs &a, hipStream_t s) {
     constexpr int NT = LPW * (L / E);
     unsigned nb = cdiv(a.nlines, LPW);
     hipLaunchKernelGGL((k_z_c2r<T, L, E, LPW>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src, (T *)a.dst,
-                       a.nlines, (const V2<T> *)a.tw);
+                       a.nlines, (const V2<T> *)a.tw, a.rev);
 }
 
 // ---- tile-shape candidates ----------------------------------------------------------------------------

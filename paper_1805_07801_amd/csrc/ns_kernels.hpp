@@ -268,7 +268,8 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, 
     __shared__ C tw[2 * L];
     load_twiddles<T>(tw, twg, 2 * L, threadIdx.x, LPW * (L / E));
     __syncthreads();
-    ns_p3_tile<T, L, E, LPW, RBC>(w6, nlines, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, nullptr, part);
+    // backwards over the lines: P2 ends at the last x planes and P4 starts at the first
+    ns_p3_tile<T, L, E, LPW, RBC>(w6, nlines, KZC, sweep_tile(blockIdx.x, gridDim.x, 1), lds, tw, nullptr, part);
 }
 
 // ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
