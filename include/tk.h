@@ -145,7 +145,7 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
  * contiguous run per XCD, 3: consecutive tiles per workgroup), 4 = one tile per workgroup
  * with each XCD sweeping its own eighth of the tiles.  Passes 3, 4, 5 are the
  * solver passes P1 (a = columns), P3 (a = lines per workgroup) and P5 (a = columns) of an
- * L^3 grid (variant 1: the tile compiled for two workgroups per CU), pass 6 the solver's
+ * L^3 grid (variant 0), pass 6 the solver's
  * Y passes P2 / P4 (a strided tile as for pass 1); solver handles created afterwards use
  * them.  a <= 0 removes the entry.  TK_EUNSUPPORTED if no such tile is compiled. */
 tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant);

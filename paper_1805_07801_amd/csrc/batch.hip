@@ -41,7 +41,7 @@ constexpr int BLDS = batch_lds_max<TK_BATCH_SIZES(TK_LIST) 16>();
 #undef TK_LIST
 
 struct BInst {
-    int n, K, KZC, pad;
+    int n, K, KZC, KZP;  // KZP: transit row length (ns_kzp)
     float2 *u, *w6, *aux, *ust;
     NsState *st;
     const float2 *tw;
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(BNT) void kb_y(const BInst *__restrict__ inst, cons
         float2 *tw = smem;                                                                                \
         load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
         __syncthreads();                                                                                  \
-        constexpr long NZH = N / 2 + 1;                                                                   \
-        strided_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, d.w6, (long)nf * N * d.KZC, d.KZC, N * NZH,  \
-                                                       NZH, inv, 1.0f, inv ? d.K : -1, inv ? -1 : d.K,    \
+        constexpr long KZP = ns_kzp<N>();                                                                 \
+        strided_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, d.w6, (long)nf * N * KZP, KZP, N * KZP,      \
+                                                       KZP, inv, 1.0f, inv ? d.K : -1, inv ? -1 : d.K,    \
                                                        w.tile, smem + N, tw);                             \
     } break;
             TK_BATCH_SIZES(TK_CASE)
@@ -167,19 +167,20 @@ __global__ void kb_set_h(const BInst *__restrict__ inst, int count) {
 }
 
 // Tiles per instance of each pass.
-static long tiles_x(int n, int K, int KZC) {
+// ncols_per_ky: KZC for P5 (kept columns), KZP for P1 (transit columns).
+static long tiles_x(int n, int K, int ncols_per_ky) {
     long W = 0;
 #define TK_W(N) if (n == N) W = BCfg<N>::W;
     TK_BATCH_SIZES(TK_W)
 #undef TK_W
-    return ((long)(2 * K + 1) * KZC + W - 1) / W;
+    return ((long)(2 * K + 1) * ncols_per_ky + W - 1) / W;
 }
-static long tiles_y(int n, int KZC, int nf) {
+static long tiles_y(int n, int cols, int nf) {
     long W = 0;
 #define TK_W(N) if (n == N) W = BCfg<N>::W;
     TK_BATCH_SIZES(TK_W)
 #undef TK_W
-    return ((long)nf * n * KZC + W - 1) / W;
+    return ((long)nf * n * cols + W - 1) / W;
 }
 static long tiles_z(int n) {
     long LPW = 0;
@@ -203,9 +204,9 @@ struct tk_nsb_s {
     BInst *dinst = nullptr;
     std::vector<NsState> hstate;
     NsState *dstate = nullptr;
-    // work lists: 0 = P1/P5, 1 = Y over 6 fields, 2 = Z lines, 3 = Y over 3 fields
-    BItem *items[4] = {nullptr, nullptr, nullptr, nullptr};
-    int nitems[4] = {0, 0, 0, 0};
+    // work lists: 0 = P5, 1 = Y over 6 fields, 2 = Z lines, 3 = Y over 3 fields, 4 = P1
+    BItem *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int nitems[5] = {0, 0, 0, 0, 0};
     std::vector<void *> bufs;
     double *dscratch = nullptr;
     hipGraph_t graph = nullptr;
@@ -231,7 +232,7 @@ static tk_status nsb_capture(tk_nsb_s *b) {
     TK_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, b->nitems[list])); };
     for (int stage = 0; stage < 2; ++stage) {
-        hipLaunchKernelGGL(kb_p1, dim3(g(0)), dim3(BNT), 0, cs, b->dinst, b->items[0], b->nitems[0], stage);
+        hipLaunchKernelGGL(kb_p1, dim3(g(4)), dim3(BNT), 0, cs, b->dinst, b->items[4], b->nitems[4], stage);
         hipLaunchKernelGGL(kb_y, dim3(g(1)), dim3(BNT), 0, cs, b->dinst, b->items[1], b->nitems[1], 6, 1);
         hipLaunchKernelGGL(kb_p3, dim3(g(2)), dim3(BNT), 0, cs, b->dinst, b->items[2], b->nitems[2], stage == 0);
         if (stage == 0)
@@ -299,7 +300,8 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
         b->bufs.push_back(aux);
         b->bufs.push_back(ust);
         // stage buffers start at zero: passes write only the 2/3-rule modes
-        if (hipMemset(aux, 0, 3 * fb) != hipSuccess || hipMemset(ust, 0, 3 * fb) != hipSuccess) {
+        if (hipMemset(aux, 0, 3 * fb) != hipSuccess || hipMemset(ust, 0, 3 * fb) != hipSuccess ||
+            hipMemset(w6, 0, 6 * fb) != hipSuccess) {
             nsb_free(b);
             return fail(TK_EHIP, "ensemble workspace clear failed");
         }
@@ -307,6 +309,7 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
         d.n = n[i];
         d.K = b->grids[i].K;
         d.KZC = b->grids[i].KZC;
+        d.KZP = b->grids[i].KZP;
         d.u = nullptr;
         d.w6 = (float2 *)w6;
         d.aux = (float2 *)aux;
@@ -327,14 +330,15 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
-    for (int list = 0; list < 4; ++list) {
+    for (int list = 0; list < 5; ++list) {
         std::vector<BItem> v;
         for (int i : order) {
             const BInst &d = b->hinst[i];
             long nt = list == 0 ? tiles_x(d.n, d.K, d.KZC)
-                      : list == 1 ? tiles_y(d.n, d.KZC, 6)
+                      : list == 1 ? tiles_y(d.n, d.KZP, 6)
                       : list == 2 ? tiles_z(d.n)
-                                  : tiles_y(d.n, d.KZC, 3);
+                      : list == 3 ? tiles_y(d.n, d.KZP, 3)
+                                  : tiles_x(d.n, d.K, d.KZP);
             for (long t = 0; t < nt; ++t) v.push_back({i, (int)t});
         }
         b->nitems[list] = (int)v.size();

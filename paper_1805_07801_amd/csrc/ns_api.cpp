@@ -3,6 +3,7 @@
 // field.  Paper, Section "Spectral Solver" (eq:NSk, eq:continuity2) and Section "Scaling
 // of Fluid spectral solver" (fourth-order Runge-Kutta, 2/3 rule, nine transforms per
 // right-hand side).
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -33,6 +34,7 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
     g->dt = dt;
     g->K = (n - 1) / 3;
     g->KZC = g->K + 1;
+    g->KZP = std::min((g->KZC + 15) / 16 * 16, n / 2 + 1);  // = ns_kzp<n>()
     g->nk = nullptr;
     for (const auto &k : ns_kernels())
         if (k.N == n && k.dt == dt) g->nk = &k;
@@ -55,12 +57,11 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
                       NsState *st_set, hipStream_t s) {
     const int n = g.n;
-    const long nzh = n / 2 + 1;
     // P1: x-inverse of u^ and omega^ = i k x u^
     g.nk->p1v[g.v1].fn(uin, w6, g.K, g.KZC, g.ax.twx, s);
     TK_TRY(launch_check("ns P1"));
     // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
-    StridedArgs y2{w6, w6, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
+    StridedArgs y2{w6, w6, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
     g.ky->fn(y2, s);
     TK_TRY(launch_check("ns P2"));
     // P3: z fused c2r -> u x omega -> r2c
@@ -72,7 +73,7 @@ tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &
         TK_TRY(launch_check("ns step size"));
     }
     // P4: y-forward of the 3 products, kept ky rows written
-    StridedArgs y4{w6, w6, 3L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 0, 1.0, -1, g.K};
+    StridedArgs y4{w6, w6, 3L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 0, 1.0, -1, g.K};
     g.ky->fn(y4, s);
     TK_TRY(launch_check("ns P4"));
     // P5: x-forward, projection, stage combine
@@ -159,6 +160,7 @@ extern "C" tk_status ns_create(tk_ns_t *out, const ns_config *cfg) {
     NsState h0{};
     // stage buffers start at zero: passes write only the 2/3-rule modes
     if (hipMemset(p->aux, 0, 3 * p->fbytes) != hipSuccess || hipMemset(p->ust, 0, 3 * p->fbytes) != hipSuccess ||
+        hipMemset(p->w6, 0, 6 * p->fbytes) != hipSuccess ||
         hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {
         ns_free(p);
         return fail(TK_EHIP, "state upload failed");

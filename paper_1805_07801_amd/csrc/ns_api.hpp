@@ -20,6 +20,7 @@ tk_status ns_scale_shells(void *u, int N, tk_dtype dt, const double *fac_dev, in
 // Everything one grid size needs to evaluate right-hand sides.
 struct NsGrid {
     int n, K, KZC;
+    int KZP;  // transit row length of the workspace fields (see ns_kzp)
     tk_dtype dt;
     FftAxes ax;
     const NsKernels *nk;

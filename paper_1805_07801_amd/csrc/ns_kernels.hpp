@@ -57,42 +57,93 @@ __device__ __forceinline__ long kept_col(long cc, int N, int K, int KZC, int NZH
     return (long)row * NZH + *kz;
 }
 
+// Transit layout of the workspace fields P1 writes and P2..P5 pass along: only the kz
+// columns the 2/3 rule keeps, padded to whole 128-byte lines, KZP = min(roundup(K + 1,
+// 16), N/2 + 1) complex values per (x, y) row, so every row segment a pass touches is
+// line-aligned (the full N/2+1 rows left partial lines at both ends of each kept run,
+// +5..19% HBM traffic by the counters).  Field f, x, y, kz at ((f N + x) N + y) KZP + kz.
+// The padding columns carry values no pass depends on.
+template <int N> constexpr int ns_kzp() {
+    const int kzc = (N - 1) / 3 + 1;
+    const int p = (kzc + 15) / 16 * 16;
+    return p < N / 2 + 1 ? p : N / 2 + 1;
+}
+
 // ---- P1: X-inverse with curl on load -------------------------------------------------------------
 // RBC = true: a fourth input field (temperature) is passed through as a seventh output.
 // ka scales the wavenumbers of the curl (2 pi / box side).
-template <typename T, int L, int E, int W, bool RBC = false>
-__device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int KZC,
-                                           long tile, V2<T> *lds, const V2<T> *tw, T ka = (T)1) {
-    using C = V2<T>;
+
+// Column of a P1 tile for thread (col, jt) = (tid % W, tid / W): column (ky, kz) of the
+// kept ky rows and the KZP transit columns; its input point i of field f at element
+// f FS + i TPL RS (uniform) + lo / sizeof(C) of the state, its output point at
+// f FSc + i TPL RSc + lo2 / sizeof(C) of the transit fields.
+struct P1Col {
+    int ky, kz;
+    unsigned lo, lo2;
+    bool valid;
+};
+
+template <typename T, int L, int E, int W>
+__device__ __forceinline__ P1Col ns_p1_col(long tile, int K) {
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
-    constexpr int TPL = L / E;
-    constexpr int ES = W + 1;
-    constexpr long FS = (long)N * N * NZH;  // field stride
-    constexpr long RS = (long)N * NZH;      // x-row stride
-    const int tid = threadIdx.x;
-    const int col = tid % W;
-    const int jt = tid / W;
-    const long ncols = (long)(2 * K + 1) * KZC;
+    constexpr int KZP = ns_kzp<N>();
+    constexpr long RS = (long)N * NZH;
+    constexpr long RSc = (long)N * KZP;
+    const int col = threadIdx.x % W;
+    const int jt = threadIdx.x / W;
+    const long ncols = (long)(2 * K + 1) * KZP;
     const long cc = tile * W + col;
-    const bool valid = cc < ncols;
-    int ky = 0, kz = 0;
-    const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
-    const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
-    const T kyd = ka * (T)ky, kzd = ka * (T)((2 * kz == N) ? 0 : kz);
-    constexpr int NOUT = RBC ? 7 : 6;
-    C a0[E], a1[E], a2[E], a3[RBC ? E : 1];
+    P1Col c;
+    c.valid = cc < ncols;
+    c.ky = c.kz = 0;
+    long row = 0;
+    if (c.valid) {
+        const long kyi = cc / KZP;
+        c.kz = (int)(cc - kyi * KZP);
+        row = kyi <= K ? kyi : kyi + N - 2 * K - 1;
+        c.ky = wave_k((int)row, N);
+    }
+    c.lo = (unsigned)((row * NZH + c.kz + (long)jt * RS) * (long)sizeof(V2<T>));
+    c.lo2 = (unsigned)((row * KZP + c.kz + (long)jt * RSc) * (long)sizeof(V2<T>));
+    return c;
+}
+
+// The kept x rows of the tile's 3 (RBC: 4) input fields.
+template <typename T, int L, int E, int W, bool RBC>
+__device__ __forceinline__ void ns_p1_load(const V2<T> *__restrict__ u, const P1Col &c, int K, V2<T> (&a0)[E],
+                                           V2<T> (&a1)[E], V2<T> (&a2)[E], V2<T> (&a3)[RBC ? E : 1]) {
+    constexpr int N = L;
+    constexpr int TPL = L / E;
+    constexpr long FS = (long)N * N * (N / 2 + 1);
+    constexpr long RS = (long)N * (N / 2 + 1);
+    const int jt = threadIdx.x / W;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        const int r = jt + i * TPL;
-        const bool ld = valid && row_kept(r, L, K);
+        const bool ld = c.valid && row_kept(jt + i * TPL, L, K);
         const long ro = (long)(i * TPL) * RS;
-        a0[i] = ld ? *at_bytes(u + ro, lo) : mk<T>(0, 0);
-        a1[i] = ld ? *at_bytes(u + FS + ro, lo) : mk<T>(0, 0);
-        a2[i] = ld ? *at_bytes(u + 2 * FS + ro, lo) : mk<T>(0, 0);
-        if constexpr (RBC) a3[i] = ld ? *at_bytes(u + 3 * FS + ro, lo) : mk<T>(0, 0);
+        a0[i] = ld ? *at_bytes(u + ro, c.lo) : mk<T>(0, 0);
+        a1[i] = ld ? *at_bytes(u + FS + ro, c.lo) : mk<T>(0, 0);
+        a2[i] = ld ? *at_bytes(u + 2 * FS + ro, c.lo) : mk<T>(0, 0);
+        if constexpr (RBC) a3[i] = ld ? *at_bytes(u + 3 * FS + ro, c.lo) : mk<T>(0, 0);
     }
+}
+
+// u^ and omega^ = i k x u^ (and theta^) transformed along x, stored to w6.
+template <typename T, int L, int E, int W, bool RBC>
+__device__ __forceinline__ void ns_p1_body(const V2<T> (&a0)[E], const V2<T> (&a1)[E], const V2<T> (&a2)[E],
+                                           const V2<T> (&a3)[RBC ? E : 1], V2<T> *__restrict__ w6, const P1Col &c,
+                                           V2<T> *lds, const V2<T> *tw, T ka) {
+    using C = V2<T>;
+    constexpr int N = L;
+    constexpr int TPL = L / E;
+    constexpr int ES = W + 1;
+    constexpr int NOUT = RBC ? 7 : 6;
+    constexpr long FSc = (long)N * N * ns_kzp<N>();
+    constexpr long RSc = (long)N * ns_kzp<N>();
+    const int col = threadIdx.x % W;
+    const int jt = threadIdx.x / W;
+    const T kyd = ka * (T)c.ky, kzd = ka * (T)((2 * c.kz == N) ? 0 : c.kz);
 #pragma unroll 1
     for (int f = 0; f < NOUT; ++f) {
         C v[E];
@@ -115,15 +166,25 @@ __device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *_
             v[i] = cconj(x);  // inverse transform as conj(DFT(conj .))
         }
         line_fft<T, L, E, ES>(v, lds + col, jt, tw);
-        if (valid) {
+        if (c.valid) {
 #pragma unroll
-            for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FS + (long)(i * TPL) * RS, lo) = cconj(v[i]);
+            for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FSc + (long)(i * TPL) * RSc, c.lo2) = cconj(v[i]);
         }
     }
 }
 
-template <typename T, int L, int E, int W, bool RBC = false, int WPE = 1>
-__global__ __launch_bounds__(W *(L / E)) __attribute__((amdgpu_waves_per_eu(WPE))) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
+template <typename T, int L, int E, int W, bool RBC = false>
+__device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int KZC,
+                                           long tile, V2<T> *lds, const V2<T> *tw, T ka = (T)1) {
+    using C = V2<T>;
+    const P1Col c = ns_p1_col<T, L, E, W>(tile, K);
+    C a0[E], a1[E], a2[E], a3[RBC ? E : 1];
+    ns_p1_load<T, L, E, W, RBC>(u, c, K, a0, a1, a2, a3);
+    ns_p1_body<T, L, E, W, RBC>(a0, a1, a2, a3, w6, c, lds, tw, ka);
+}
+
+template <typename T, int L, int E, int W, bool RBC = false>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
                                                        int KZC, const V2<T> *__restrict__ twg, T ka) {
     using C = V2<T>;
     __shared__ C lds[L * (W + 1)];
@@ -134,8 +195,9 @@ __global__ __launch_bounds__(W *(L / E)) __attribute__((amdgpu_waves_per_eu(WPE)
 }
 
 // ---- P3: fused Z pass ------------------------------------------------------------------------------
-// Lines l = x * N + y of the 6 fields in w6 (kz < KZC nonzero); outputs c = u x omega
-// transformed back, kz < KZC, into fields 0..2 of w6 (in place: each workgroup reads all
+// Lines l = x * N + y of the 6 transit fields in w6 (kz < KZC read, the rest taken as
+// zero); outputs c = u x omega transformed back, kz < KZP, into fields 0..2 of w6 (in
+// place: each workgroup reads all
 // six fields of its lines before it writes).  lds: LPW lines of lds_line_len<L>().
 // RBC = true: a seventh input (temperature theta) gives three more outputs q = u theta.
 // CFL maximum of |u|_1 over the tile's samples: written to part[tile] (one value per
@@ -149,7 +211,8 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     constexpr int NZH = L + 1;
     constexpr int TPL = L / E;
     constexpr int LL = lds_line_len<L>();
-    constexpr long FS = (long)N * N * NZH;
+    constexpr int KZP = ns_kzp<N>();          // transit row length
+    constexpr long FS = (long)N * N * KZP;      // transit field stride
     const int tid = threadIdx.x;
     const int ln = tid / TPL;
     const int jt = tid % TPL;
@@ -164,7 +227,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     // the next field's samples are loaded before the current field is transformed, so the
     // loads overlap the transform (the exchange waits only on LDS traffic)
     auto load = [&](C(&x)[E], int f) {
-        const C *s = w6 + f * FS + (valid ? l : 0) * NZH;
+        const C *s = w6 + f * FS + (valid ? l : 0) * KZP;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
@@ -232,11 +295,11 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
         C zm[E];
         mirror<T, L, E>(v, zm, jt);
         if (valid) {
-            C *o = w6 + f * FS + l * NZH;
+            C *o = w6 + f * FS + l * KZP;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const int k = jt + i * TPL;
-                if (k < KZC) {
+                if (k < KZP) {  // whole transit rows (the padding values are never used)
                     const C zk = v[i];
                     const C zc = cconj(zm[i]);
                     const C a = cadd(zk, zc);
@@ -285,7 +348,9 @@ struct P5Args {
     int mode;
 };
 
-template <typename T, int L, int E, int W>
+// PRE: the stage combine's operands (u, and aux where the mode reads it) are loaded with
+// the input, before the transforms, instead of after them.
+template <typename T, int L, int E, int W, bool PRE = false>
 __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3, V2<T> *u,
                                            V2<T> *aux, V2<T> *ust, V2<T> *out, const NsState *__restrict__ st,
                                            double nu, int mode, int K, int KZC, long tile, V2<T> *lds,
@@ -305,13 +370,35 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane);
+    // in the transit fields c3 at f FSc + i TPL RSc + loc / sizeof(C)
+    constexpr int KZP = ns_kzp<N>();
+    constexpr long FSc = (long)N * N * KZP;
+    constexpr long RSc = (long)N * KZP;
     const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
+    const unsigned loc = (unsigned)(((j / NZH) * KZP + kz + (long)jt * RSc) * (long)sizeof(C));
     C cf[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) cf[f][i] = valid ? *at_bytes(c3 + f * FS + (long)(i * TPL) * RS, lo) : mk<T>(0, 0);
+        for (int i = 0; i < E; ++i)
+            cf[f][i] = valid ? *at_bytes(c3 + f * FSc + (long)(i * TPL) * RSc, loc) : mk<T>(0, 0);
+    }
+    constexpr int PE = PRE ? E : 1;
+    C pu[3][PE], pa[3][PE];
+    if constexpr (PRE) {
+        const bool need_u = valid && mode != NS_RHS;
+        const bool need_aux = valid && (mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const bool kept = row_kept(jt + i * TPL, L, K);
+                const long ro = f * FS + (long)(i * TPL) * RS;
+                pu[f][i] = (need_u && kept) ? *at_bytes(u + ro, lo) : mk<T>(0, 0);
+                pa[f][i] = (need_aux && kept) ? *at_bytes(aux + ro, lo) : mk<T>(0, 0);
+            }
+        }
     }
     // unrolled over the fields: a run-time field index into cf would put it in scratch
 #pragma unroll
@@ -353,7 +440,8 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const T th = (T)h;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const C uu = *at(u, f);
+                const C uu = PRE ? pu[f][PRE ? i : 0] : *at(u, f);
+                const C ax = PRE ? pa[f][PRE ? i : 0] : mk<T>(0, 0);
                 const C n = nn[f];
                 switch (mode) {
                 case RK2_S1:
@@ -361,22 +449,22 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
                     *at(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
                 case RK2_S2:
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*at(aux, f), e1), n), (T)0.5 * th));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(PRE ? ax : *at(aux, f), e1), n), (T)0.5 * th));
                     break;
                 case RK4_S1:
                     *at(aux, f) = cscale(n, e1);
                     *at(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
                 case RK4_S2:
-                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
+                    *at(aux, f) = cadd(PRE ? ax : *at(aux, f), cscale(n, (T)2 * e2));
                     *at(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
-                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
+                    *at(aux, f) = cadd(PRE ? ax : *at(aux, f), cscale(n, (T)2 * e2));
                     *at(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*at(aux, f), n), th / (T)6));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(PRE ? ax : *at(aux, f), n), th / (T)6));
                     break;
                 }
             }
@@ -384,7 +472,7 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
     }
 }
 
-template <typename T, int L, int E, int W>
+template <typename T, int L, int E, int W, bool PRE = false>
 __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3,
                                                        V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
                                                        const NsState *__restrict__ st, double nu, int mode, int K,
@@ -394,8 +482,8 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ 
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
     __syncthreads();
-    ns_p5_tile<T, L, E, W>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds,
-                           tw);
+    ns_p5_tile<T, L, E, W, PRE>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x),
+                                lds, tw);
 }
 
 // ---- P5 of the Boussinesq (RBC) right-hand side ----------------------------------------------------
@@ -423,8 +511,13 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
     const bool valid = cc < ncols;
     int ky = 0, kz = 0;
     const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane)
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane);
+    // in the transit fields c6 at f FSc + i TPL RSc + loc / sizeof(C)
+    constexpr int KZP = ns_kzp<N>();
+    constexpr long FSc = (long)N * N * KZP;
+    constexpr long RSc = (long)N * KZP;
     const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
+    const unsigned loc = (unsigned)(((j / NZH) * KZP + kz + (long)jt * RSc) * (long)sizeof(C));
     C cf[3][E], nt[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) nt[i] = mk<T>(0, 0);
@@ -432,7 +525,7 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
     for (int f = 0; f < 6; ++f) {
         C v[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = valid ? *at_bytes(c6 + f * FS + (long)(i * TPL) * RS, lo) : mk<T>(0, 0);
+        for (int i = 0; i < E; ++i) v[i] = valid ? *at_bytes(c6 + f * FSc + (long)(i * TPL) * RSc, loc) : mk<T>(0, 0);
         line_fft<T, L, E, ES>(v, lds + col, jt, tw);
         if (f < 3) {
 #pragma unroll
@@ -568,10 +661,10 @@ using NsP1Fn = void (*)(const void *u, void *w6, int K, int KZC, const void *tw,
 using NsP3Fn = void (*)(void *w6, long nlines, int KZC, const void *tw, float *part, hipStream_t s);
 using NsP5Fn = void (*)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
 template <typename F> struct NsVar {
-    int a, E, v;  // v = 1: compiled for 4 waves per SIMD (at most 128 registers a thread)
+    int a, E, v;  // v: variant of one shape (0: the only one compiled)
     F fn;
 };
-constexpr int NS_MAXVAR = 4;
+constexpr int NS_MAXVAR = 6;
 
 struct NsKernels {
     int N;
@@ -589,21 +682,21 @@ struct NsKernels {
 };
 const std::vector<NsKernels> &ns_kernels();
 
-template <typename T, int N, int E, int W, int WPE = 1>
+template <typename T, int N, int E, int W>
 void launch_ns_p1(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
-    const long ncols = (long)(2 * K + 1) * KZC;
-    hipLaunchKernelGGL((k_ns_p1<T, N, E, W, false, WPE>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
-                       (const V2<T> *)u, (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
+    const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
+    hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)u,
+                       (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
 }
 template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long nlines, int KZC, const void *tw,
                                                                  float *part, hipStream_t s) {
     hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
                        (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, part);
 }
-template <typename T, int N, int E, int W> void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw,
-                                                             hipStream_t s) {
+template <typename T, int N, int E, int W, bool PRE = false>
+void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
     const long ncols = (long)(2 * K + 1) * KZC;
-    hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
+    hipLaunchKernelGGL((k_ns_p5<T, N, E, W, PRE>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
                        (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, (V2<T> *)a.ust, (V2<T> *)a.out, a.st,
                        a.nu, a.mode, K, KZC, (const V2<T> *)tw);
 }
@@ -611,20 +704,19 @@ template <typename T, int N, int E, int W> void launch_ns_p5(const P5Args &a, in
 // Column-pass variant (E, W) of P1 / P5 (FP32, N >= 128): kept when it differs from the
 // default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  P1 holds
 // three input fields per thread, so it only gets 512-thread variants (a 1024-thread
-// workgroup leaves 128 registers per thread); P5 gets 512 and 1024.
+// workgroup leaves 128 registers per thread); P5 gets 512 and 1024.  (Persistent P1
+// workgroups loading the next tile ahead measured 1.5x slower at 512^3.)
 template <typename T, int N, int E, int W> constexpr bool ns_x_var_ok() {
     return sizeof(T) == 4 && N >= 128 && E <= N && N % E == 0 && rplan_ok(N, E) && W >= 1 &&
            W * (N / E) >= 64 && W * (N / E) <= 1024 && (long)(N * (W + 1) + N) * 2 * (long)sizeof(T) <= 163840 &&
            !(E == ns_x_E<T>(N) && W == ns_x_W<T>(N));
 }
 template <typename T, int N, int E, int W> void add_ns_p1_var(NsKernels &k) {
-    if constexpr (ns_x_var_ok<T, N, E, W>() && W * (N / E) <= 512) {
-        k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
-        // the same tile held to 128 registers, so two 512-thread workgroups share a CU
-        k.p1v[k.np1++] = {W, E, 1, &launch_ns_p1<T, N, E, W, 4>};
-    }
+    if constexpr (ns_x_var_ok<T, N, E, W>() && W * (N / E) <= 512) k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
 }
 template <typename T, int N, int E, int W> void add_ns_p5_var(NsKernels &k) {
+    // (a variant loading the stage combine's operands with the input, before the
+    // transforms, measured 10% slower at 512^3: the registers it takes cost occupancy)
     if constexpr (ns_x_var_ok<T, N, E, W>()) k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
 }
 // Line-pass variant E2 of P3 (FP32, N >= 128; L2 = N / 2 points per complex line, 256
@@ -660,7 +752,7 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     add_ns_p5_var<T, N, Ed, 1024 * Ed / N>(k);
     add_ns_z_var<T, N, default_E(L2) / 2>(k);
     k.p1r = [](const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s) {
-        const long ncols = (long)(2 * K + 1) * KZC;
+        const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
         hipLaunchKernelGGL((k_ns_p1<T, N, E, W, true>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
                            (const V2<T> *)u, (V2<T> *)w7, K, KZC, (const V2<T> *)tw, (T)ka);
     };

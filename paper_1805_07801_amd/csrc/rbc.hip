@@ -86,10 +86,9 @@ static tk_status rbc_rhs_eval(tk_rbc_s *p, const void *uin, void *u, void *out, 
                               hipStream_t s) {
     const NsGrid &g = p->g;
     const int n = g.n;
-    const long nzh = n / 2 + 1;
     g.nk->p1r(uin, p->w7, g.K, g.KZC, g.ax.twx, p->ka, s);
     TK_TRY(launch_check("rbc P1"));
-    StridedArgs y2{p->w7, p->w7, 7L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
+    StridedArgs y2{p->w7, p->w7, 7L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
     g.ky->fn(y2, s);
     TK_TRY(launch_check("rbc P2"));
     g.nk->p3r(p->w7, (long)n * n, g.KZC, g.ax.twz, first_stage ? p->umax_part : nullptr, s);
@@ -99,7 +98,7 @@ static tk_status rbc_rhs_eval(tk_rbc_s *p, const void *uin, void *u, void *out, 
         hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(1024), 0, s, p->st, p->umax_part, nparts);
         TK_TRY(launch_check("rbc step size"));
     }
-    StridedArgs y4{p->w7, p->w7, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 0, 1.0, -1, g.K};
+    StridedArgs y4{p->w7, p->w7, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 0, 1.0, -1, g.K};
     g.ky->fn(y4, s);
     TK_TRY(launch_check("rbc P4"));
     g.nk->p5r(p->w7, uin, u, p->aux, p->ust, out, p->st, p->nu_a, p->kap_a, p->ka, mode, g.K, g.KZC, g.ax.twx, s);
@@ -138,6 +137,7 @@ extern "C" tk_status rbc_create(tk_rbc_t *out, const rbc_config *cfg) {
         hipMalloc((void **)&p->umax_part, sizeof(float) * n * n) != hipSuccess ||
         hipMalloc((void **)&p->dscratch, sizeof(double) * 4 * (NS_DIAG_BLOCKS + 1)) != hipSuccess ||
         hipMemset(p->aux, 0, 4 * p->fbytes) != hipSuccess || hipMemset(p->ust, 0, 4 * p->fbytes) != hipSuccess ||
+        hipMemset(p->w7, 0, 7 * p->fbytes) != hipSuccess ||
         hipMemcpy(p->st, &h0, sizeof(h0), hipMemcpyHostToDevice) != hipSuccess) {
         rbc_free(p);
         return fail(TK_ENOMEM, "convection solver workspace allocation failed");

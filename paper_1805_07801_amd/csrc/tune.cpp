@@ -347,8 +347,7 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
     // P2 (the Y pass with the solver's row masks and kept columns), in place on 6 fields;
     // candidates are all strided tiles of length n
     {
-        const long nzh = n / 2 + 1;
-        StridedArgs y2{B.w6, B.w6, 6L * n * g.KZC, g.KZC, (long)n * nzh, nzh, g.ax.twy, 1, 1.0, g.K, -1};
+        StridedArgs y2{B.w6, B.w6, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
         float best = 1e30f;
         int ba = 0, bE = 0, bv = 0;
         bool first = true;
@@ -371,7 +370,8 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
         }
         finish(6, ba, bE, bv, best);
     }
-    // P5 (right-hand-side mode): 3 fields of in6 -> out
+    // P5: checked in right-hand-side mode (3 fields of in6 -> out), timed as the second RK2
+    // stage (reads u and aux, writes u; with the zeroed step state h = 0 leaves u as it is)
     {
         float best = 1e30f;
         int ba = 0, bE = 0, bv = 0;
@@ -380,6 +380,10 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
         a.out = B.out;
         a.st = B.st;
         a.mode = NS_RHS;
+        P5Args a2 = a;
+        a2.mode = RK2_S2;
+        a2.u = B.u;
+        a2.aux = (char *)B.in6 + 3 * fb;
         for (int i = 0; i < k->np5; ++i) {
             const auto &v = k->p5v[i];
             TK_HIP_CHECK(hipMemsetAsync(B.out, 0, 3 * fb, s));
@@ -389,8 +393,9 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
             bool ok = true;
             if (i > 0) TK_TRY(check(B.out, B.ref, 6 * nf, &ok));
             float ms;
-            TK_TRY(time_it([&] { v.fn(a, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
-            snprintf(line, sizeof(line), "pass p5 N=%d W=%d E=%d: %.4f ms %s\n", n, v.a, v.E, ms, ok ? "ok" : "REJECTED");
+            TK_TRY(time_it([&] { v.fn(a2, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p5 N=%d W=%d E=%d v=%d: %.4f ms %s\n", n, v.a, v.E, v.v, ms,
+                     ok ? "ok" : "REJECTED");
             rep += line;
             if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
         }
