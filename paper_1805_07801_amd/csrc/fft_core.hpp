@@ -169,7 +169,9 @@ template <int ES> __device__ __forceinline__ void exchange_sync() {
 // Column tiles (ES > 1): every thread of the workgroup must call it (it contains
 // barriers); on exit the LDS may be reused only after a barrier.  Contiguous lines
 // (ES == 1): the lanes of a line call it together and may reuse their LDS row at once.
-template <typename T, int L, int E, int ES, int TS = 1, int S = 0>
+// TWP: twiddle powers by multiplication (for LDS-bound callers; HBM-bound passes keep the
+// table reads, which cost fewer registers).
+template <typename T, int L, int E, int ES, int TS = 1, int S = 0, bool TWP = false>
 __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw) {
     using C = V2<T>;
     constexpr RPlan P = make_rplan(L, E);
@@ -183,8 +185,21 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
         const int j = jt + b * TPL;
         const int k = j % NS;
         if constexpr (NS > 1) {
+            if constexpr (TWP) {
+                // leg m takes W^m, W = W_{NS R}^k: one table read, the powers by
+                // multiplication (R - 2 complex products instead of R - 2 more LDS reads;
+                // the error grows by about one rounding per power)
+                const C w = tw[k * (L / (NS * R)) * TS];
+                C wm = w;
 #pragma unroll
-            for (int m = 1; m < R; ++m) v[b + m * NB] = cmul(v[b + m * NB], tw[k * m * (L / (NS * R)) * TS]);
+                for (int m = 1; m < R; ++m) {
+                    v[b + m * NB] = cmul(v[b + m * NB], wm);
+                    if (m + 1 < R) wm = cmul(wm, w);
+                }
+            } else {
+#pragma unroll
+                for (int m = 1; m < R; ++m) v[b + m * NB] = cmul(v[b + m * NB], tw[k * m * (L / (NS * R)) * TS]);
+            }
         }
         dft_legs<R, NB>(v, b);
     }
@@ -201,7 +216,7 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
         exchange_sync<ES>();
-        line_fft<T, L, E, ES, TS, S + 1>(v, d, jt, tw);
+        line_fft<T, L, E, ES, TS, S + 1, TWP>(v, d, jt, tw);
     }
 }
 

@@ -255,7 +255,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             const C b = cmul(cconj(tw[k]), csub(xk, xc));
             v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
         }
-        line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+        line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const C w = mk<T>(v[i].x, -v[i].y);
@@ -291,7 +291,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = c[f][i];
-        line_fft<T, L, E, 1, 2>(v, d, jt, tw);
+        line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw);
         C zm[E];
         mirror<T, L, E>(v, zm, jt);
         if (valid) {
