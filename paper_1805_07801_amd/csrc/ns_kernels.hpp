@@ -165,7 +165,7 @@ __device__ __forceinline__ void ns_p1_body(const V2<T> (&a0)[E], const V2<T> (&a
             }
             v[i] = cconj(x);  // inverse transform as conj(DFT(conj .))
         }
-        line_fft<T, L, E, ES>(v, lds + col, jt, tw);
+        line_fft<T, L, E, ES, 1, 0, true>(v, lds + col, jt, tw);
         if (c.valid) {
 #pragma unroll
             for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FSc + (long)(i * TPL) * RSc, c.lo2) = cconj(v[i]);
