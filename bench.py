@@ -321,7 +321,7 @@ def main():
             "roundtrip_rel_l2": err2,
         }
     if not args.no_ns and hasattr(tk, "NS"):
-        sps, e = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 5), 2)
+        sps, e = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 2), 2)
         out["ns512_rk2_steps_per_s"] = round(sps, 2)
         out["ns512_energy_after"] = e
     if not args.no_extra:
