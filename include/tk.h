@@ -139,15 +139,16 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
                          int report_len);
 
 /* Force the tile of (L, dt, pass): pass 0 = Z (a = threads per workgroup), 1 = Y and
- * 2 = X (a = columns per tile); E = points per thread; variant (strided passes; 0 for Z)
- * 0 = one tile per workgroup, 1..3 = persistent workgroups that issue the next tile's loads
- * before transforming the current one (1: tiles dealt round-robin, 2: round-robin with a
- * contiguous run per XCD, 3: consecutive tiles per workgroup), 4 = one tile per workgroup
- * with each XCD sweeping its own eighth of the tiles.  Passes 3, 4, 5 are the
- * solver passes P1 (a = columns), P3 (a = lines per workgroup) and P5 (a = columns) of an
- * L^3 grid (variant 0), pass 6 the solver's
- * Y passes P2 / P4 (a strided tile as for pass 1); solver handles created afterwards use
- * them.  a <= 0 removes the entry.  TK_EUNSUPPORTED if no such tile is compiled. */
+ * 2 = X (a = columns per tile); E = points per thread; variant (strided passes; 0 for Z):
+ * 0 = one tile per workgroup sweeping the tiles once; 1..3 = persistent workgroups that
+ * issue the next tile's loads before transforming the current one (1: tiles dealt
+ * round-robin, 2: round-robin with a contiguous run per XCD, 3: consecutive tiles per
+ * workgroup); 4 = one tile per workgroup, each XCD sweeping its own eighth of the tiles;
+ * 5, 6 = 0 and 4 with split exchanges (real, then imaginary parts through half the LDS).
+ * Passes 3, 4, 5 are the solver passes P1 (a = columns), P3 (a = lines per workgroup) and
+ * P5 (a = columns) of an L^3 grid (variant 0), pass 6 the solver's Y passes P2 / P4 (a
+ * strided tile as for pass 1); solver handles created afterwards use them.  a <= 0
+ * removes the entry.  TK_EUNSUPPORTED if no such tile is compiled. */
 tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant);
 
 /* Autotune the solver passes P1, P2 / P4, P3 and P5 of an n^3 grid in dtype dt: every

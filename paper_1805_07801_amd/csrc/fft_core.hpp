@@ -171,7 +171,10 @@ template <int ES> __device__ __forceinline__ void exchange_sync() {
 // (ES == 1): the lanes of a line call it together and may reuse their LDS row at once.
 // TWP: twiddle powers by multiplication (for LDS-bound callers; HBM-bound passes keep the
 // table reads, which cost fewer registers).
-template <typename T, int L, int E, int ES, int TS = 1, int S = 0, bool TWP = false>
+// SPLIT: exchange the real parts, then the imaginary parts, through an LDS line of scalars
+// (d is then a T pointer in disguise, element e at ((T *)d)[lds_at<ES>(e)]): half the LDS
+// of a column tile, so more workgroups fit on a CU, for two more barriers per exchange.
+template <typename T, int L, int E, int ES, int TS = 1, int S = 0, bool TWP = false, bool SPLIT = false>
 __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw) {
     using C = V2<T>;
     constexpr RPlan P = make_rplan(L, E);
@@ -204,19 +207,42 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
         dft_legs<R, NB>(v, b);
     }
     if constexpr (S + 1 < P.n) {
+        if constexpr (SPLIT) {
+            T *ds = reinterpret_cast<T *>(d);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int j = jt + b * TPL;
-            const int k = j % NS;
-            const int base = (j - k) * R + k;
+            for (int part = 0; part < 2; ++part) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
+                for (int b = 0; b < NB; ++b) {
+                    const int j = jt + b * TPL;
+                    const int k = j % NS;
+                    const int base = (j - k) * R + k;
+#pragma unroll
+                    for (int m = 0; m < R; ++m)
+                        ds[lds_at<ES>(base + m * NS)] = part ? v[b + m * NB].y : v[b + m * NB].x;
+                }
+                exchange_sync<ES>();
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    if (part) v[i].y = ds[lds_at<ES>(jt + i * TPL)];
+                    else v[i].x = ds[lds_at<ES>(jt + i * TPL)];
+                }
+                exchange_sync<ES>();
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = jt + b * TPL;
+                const int k = j % NS;
+                const int base = (j - k) * R + k;
+#pragma unroll
+                for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
+            }
+            exchange_sync<ES>();
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
+            exchange_sync<ES>();
         }
-        exchange_sync<ES>();
-#pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
-        exchange_sync<ES>();
-        line_fft<T, L, E, ES, TS, S + 1, TWP>(v, d, jt, tw);
+        line_fft<T, L, E, ES, TS, S + 1, TWP, SPLIT>(v, d, jt, tw);
     }
 }
 

@@ -17,6 +17,12 @@ template <typename T, int L, int CE, int CN> void add_strided(std::vector<Stride
         constexpr int W = NT * E / L;
         v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided<T, L, E, W>, 0});
         v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided<T, L, E, W, 1>, 4});
+        // split exchanges where the full LDS tile leaves room for one or two workgroups per CU
+        if constexpr (sizeof(T) == 4 && L >= 512 && strided_lds<T>(L, W) > 65536) {
+            constexpr int lds_split = (L * (W + 1) + 2 * L) * (int)sizeof(T);
+            v.push_back({L, dtype_of<T>(), W, E, NT, lds_split, &launch_strided<T, L, E, W, 0, true>, 5});
+            v.push_back({L, dtype_of<T>(), W, E, NT, lds_split, &launch_strided<T, L, E, W, 1, true>, 6});
+        }
         // the persistent variant holds two tiles' points per thread: kept where they take
         // under half of the registers a thread has at this workgroup size (512 / (NT / 256))
         if constexpr (E <= 32 && 2 * E * 2 * (int)sizeof(T) / 4 <= 512 / (NT / 256) / 2 - 8)

@@ -35,7 +35,8 @@ using StridedFn = void (*)(const StridedArgs &, hipStream_t);
 
 // var 0: one tile per workgroup, one sweep over the tiles; var 1..3: persistent workgroups
 // with the next tile's loads issued ahead (k_strided_pp), tile order var; var 4: one tile
-// per workgroup, each XCD sweeping its own eighth of the tiles.
+// per workgroup, each XCD sweeping its own eighth of the tiles; var 5, 6: as 0 and 4 with
+// split exchanges (real and imaginary parts in turn through half the LDS).
 struct StridedKernel {
     int L;
     tk_dtype dt;
@@ -161,9 +162,10 @@ __device__ __forceinline__ void strided_store(const V2<T> (&v)[E], V2<T> *dst, c
     }
 }
 
-// One column tile: W columns x L points.  lds: L (W + 1) complex for the exchanges;
-// tw: the W_L^j table already in LDS.  Contains barriers: every thread calls it.
-template <typename T, int L, int E, int W, bool MASK = true>
+// One column tile: W columns x L points.  lds: L (W + 1) complex for the exchanges (SPLIT:
+// L (W + 1) scalars); tw: the W_L^j table already in LDS.  Contains barriers: every thread
+// calls it.
+template <typename T, int L, int E, int W, bool MASK = true, bool SPLIT = false>
 __device__ __forceinline__ void strided_tile(const V2<T> *src, V2<T> *dst, long ncols, long CB, long SO, long SI,
                                              int inv, T scale, int kl, int ks, long tile, V2<T> *lds,
                                              const V2<T> *tw) {
@@ -176,41 +178,43 @@ __device__ __forceinline__ void strided_tile(const V2<T> *src, V2<T> *dst, long 
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i].y = -v[i].y;
     }
-    line_fft<T, L, E, ES>(v, lds + threadIdx.x % W, threadIdx.x / W, tw);
+    C *d = SPLIT ? reinterpret_cast<C *>(reinterpret_cast<T *>(lds) + threadIdx.x % W) : lds + threadIdx.x % W;
+    line_fft<T, L, E, ES, 1, 0, false, SPLIT>(v, d, threadIdx.x / W, tw);
     strided_store<T, L, E, W, MASK>(v, dst, a, SI, inv, scale, ks);
 }
 
 template <typename T, int L, int E, int W> constexpr int strided_lds_elems() { return L * strided_es<L, E, W>(); }
 
-template <typename T, int L, int E, int W, bool MASK>
+template <typename T, int L, int E, int W, bool MASK, bool SPLIT = false>
 __global__ __launch_bounds__(W *(L / E)) void k_strided(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                          long SO, long SI, const V2<T> *__restrict__ twg,
                                                          int inv, T scale, int kl, int ks, int rev,
                                                          int regions) {
     using C = V2<T>;
     constexpr int NT = W * (L / E);
-    __shared__ C lds[strided_lds_elems<T, L, E, W>()];
+    __shared__ C lds[SPLIT ? (strided_lds_elems<T, L, E, W>() + 1) / 2 : strided_lds_elems<T, L, E, W>()];
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, NT);
     __syncthreads();
     // regions: each XCD sweeps its own eighth of the tiles (the 8 sweeps run side by side)
     unsigned t = regions ? xcd_tile(blockIdx.x, gridDim.x) : sweep_tile(blockIdx.x, gridDim.x, 0);
     if (rev) t = gridDim.x - 1 - t;
-    strided_tile<T, L, E, W, MASK>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks, t, lds, tw);
+    strided_tile<T, L, E, W, MASK, SPLIT>(src, dst, ncols, CB, SO, SI, inv, scale, kl, ks, t, lds, tw);
 }
 
 // Row masks select the MASK instantiation; plain transforms run the branch-free one.
-// REGIONS: tile order by XCD regions instead of one sweep (variant 4).
-template <typename T, int L, int E, int W, int REGIONS = 0>
+// REGIONS: tile order by XCD regions instead of one sweep (variants 4, 6); SPLIT: the
+// exchanges move real and imaginary parts separately through half the LDS (5, 6).
+template <typename T, int L, int E, int W, int REGIONS = 0, bool SPLIT = false>
 void launch_strided(const StridedArgs &a, hipStream_t s) {
     constexpr int NT = W * (L / E);
     unsigned nb = cdiv(a.ncols, W);
     if (a.kl >= 0 || a.ks >= 0)
-        hipLaunchKernelGGL((k_strided<T, L, E, W, true>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
+        hipLaunchKernelGGL((k_strided<T, L, E, W, true, SPLIT>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
                            (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
                            a.ks, a.rev, REGIONS);
     else
-        hipLaunchKernelGGL((k_strided<T, L, E, W, false>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
+        hipLaunchKernelGGL((k_strided<T, L, E, W, false, SPLIT>), dim3(nb), dim3(NT), 0, s, (const V2<T> *)a.src,
                            (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
                            a.ks, a.rev, REGIONS);
 }
