@@ -1,11 +1,14 @@
 // Ensembles of independent Navier-Stokes solves of mixed grid sizes.
 //
-// Each pass of a right-hand side (P1 .. P5, see ns_kernels.hpp) is ONE persistent kernel
-// for the whole ensemble: a grid sized to the GPU walks a work list of (instance, tile)
-// items, largest grids first, and dispatches on the item's grid size to the same tile
-// functions the single solver uses.  One IF-RK2 step of all members is captured once as
-// a HIP graph (eleven kernels) and replayed, so a step costs one graph launch.
+// The members are grouped by grid size.  Each pass of a right-hand side (P1 .. P5, see
+// ns_kernels.hpp) is one persistent kernel per size class: a grid sized to the GPU walks
+// the class's work list of (instance, tile) items with the same tile functions the single
+// solver uses.  The classes run their chains of passes on separate streams of one HIP
+// graph (one IF-RK2 step of all members), captured once and replayed, so a step costs one
+// graph launch and the classes' kernels overlap.
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <cmath>
 #include <new>
 
@@ -30,16 +33,6 @@ template <int N> struct BCfg {
     static_assert(W * (N / E) == BNT && LPW * (L2 / E2) == BNT, "batch tile shape");
 };
 
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-template <int... Ns> constexpr int batch_lds_max() {
-    int m = 0;
-    ((m = cmax(m, cmax(BCfg<Ns>::lds_x, BCfg<Ns>::lds_z))), ...);
-    return m;
-}
-#define TK_LIST(N) N,
-constexpr int BLDS = batch_lds_max<TK_BATCH_SIZES(TK_LIST) 16>();
-#undef TK_LIST
-
 struct BInst {
     int n, K, KZC, KZP;  // KZP: transit row length (ns_kzp)
     float2 *u, *w6, *aux, *ust;
@@ -60,100 +53,78 @@ static bool batch_size_ok(int n) {
 }
 
 // ---- persistent pass kernels -------------------------------------------------------------------
+// One kernel per pass and grid size: a size class's work list holds the (instance, tile)
+// items of its members only, so each kernel's registers and LDS fit its own tiles (a single
+// kernel switching over every size took the largest size's registers for all of them).
+template <int N>
 __global__ __launch_bounds__(BNT) void kb_p1(const BInst *__restrict__ inst, const BItem *__restrict__ items,
                                              int nitems, int stage2) {
-    __shared__ float2 smem[BLDS];
+    __shared__ float2 smem[BCfg<N>::lds_x];
+    float2 *tw = smem;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem w = items[it];
         const BInst &d = inst[w.inst];
         const float2 *in = stage2 ? d.ust : d.u;
         __syncthreads();
-        switch (d.n) {
-#define TK_CASE(N)                                                                                        \
-    case N: {                                                                                             \
-        float2 *tw = smem;                                                                                \
-        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
-        __syncthreads();                                                                                  \
-        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, d.KZC, w.tile, smem + N, tw);         \
-    } break;
-            TK_BATCH_SIZES(TK_CASE)
-#undef TK_CASE
-        }
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
+        __syncthreads();
+        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, d.KZC, w.tile, smem + N, tw);
     }
 }
 
+template <int N>
 __global__ __launch_bounds__(BNT) void kb_y(const BInst *__restrict__ inst, const BItem *__restrict__ items,
                                             int nitems, int nf, int inv) {
-    __shared__ float2 smem[BLDS];
+    __shared__ float2 smem[BCfg<N>::lds_x];
+    float2 *tw = smem;
+    constexpr long KZP = ns_kzp<N>();
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem w = items[it];
         const BInst &d = inst[w.inst];
         __syncthreads();
-        switch (d.n) {
-#define TK_CASE(N)                                                                                        \
-    case N: {                                                                                             \
-        float2 *tw = smem;                                                                                \
-        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
-        __syncthreads();                                                                                  \
-        constexpr long KZP = ns_kzp<N>();                                                                 \
-        strided_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, d.w6, (long)nf * N * KZP, KZP, N * KZP,      \
-                                                       KZP, inv, 1.0f, inv ? d.K : -1, inv ? -1 : d.K,    \
-                                                       w.tile, smem + N, tw);                             \
-    } break;
-            TK_BATCH_SIZES(TK_CASE)
-#undef TK_CASE
-        }
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
+        __syncthreads();
+        strided_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, d.w6, (long)nf * N * KZP, KZP, N * KZP, KZP, inv, 1.0f,
+                                                       inv ? d.K : -1, inv ? -1 : d.K, w.tile, smem + N, tw);
     }
 }
 
+template <int N>
 __global__ __launch_bounds__(BNT) void kb_p3(const BInst *__restrict__ inst, const BItem *__restrict__ items,
                                              int nitems, int with_umax) {
-    __shared__ float2 smem[BLDS];
+    __shared__ float2 smem[BCfg<N>::lds_z];
+    float2 *tw = smem;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem w = items[it];
         const BInst &d = inst[w.inst];
         unsigned *um = with_umax ? &d.st->umax : nullptr;
         __syncthreads();
-        switch (d.n) {
-#define TK_CASE(N)                                                                                        \
-    case N: {                                                                                             \
-        float2 *tw = smem;                                                                                \
-        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
-        __syncthreads();                                                                                  \
-        ns_p3_tile<float, N / 2, BCfg<N>::E2, BCfg<N>::LPW>(d.w6, (long)N * N, d.KZC, w.tile, smem + N,   \
-                                                            tw, um);                                      \
-    } break;
-            TK_BATCH_SIZES(TK_CASE)
-#undef TK_CASE
-        }
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
+        __syncthreads();
+        ns_p3_tile<float, N / 2, BCfg<N>::E2, BCfg<N>::LPW>(d.w6, (long)N * N, d.KZC, w.tile, smem + N, tw, um);
     }
 }
 
+template <int N>
 __global__ __launch_bounds__(BNT) void kb_p5(const BInst *__restrict__ inst, const BItem *__restrict__ items,
                                              int nitems, int mode) {
-    __shared__ float2 smem[BLDS];
+    __shared__ float2 smem[BCfg<N>::lds_x];
+    float2 *tw = smem;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem w = items[it];
         const BInst &d = inst[w.inst];
         __syncthreads();
-        switch (d.n) {
-#define TK_CASE(N)                                                                                        \
-    case N: {                                                                                             \
-        float2 *tw = smem;                                                                                \
-        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);                                              \
-        __syncthreads();                                                                                  \
-        ns_p5_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, nullptr, d.u, d.aux, d.ust, nullptr, d.st,     \
-                                                     d.nu, mode, d.K, d.KZC, w.tile, smem + N, tw);       \
-    } break;
-            TK_BATCH_SIZES(TK_CASE)
-#undef TK_CASE
-        }
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
+        __syncthreads();
+        ns_p5_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, nullptr, d.u, d.aux, d.ust, nullptr, d.st, d.nu, mode,
+                                                     d.K, d.KZC, w.tile, smem + N, tw);
     }
 }
 
-__global__ void kb_set_h(const BInst *__restrict__ inst, int count) {
+// Step size of the members of grid size n (the other members belong to other size classes).
+__global__ void kb_set_h(const BInst *__restrict__ inst, int count, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) {
+    if (i < count && inst[i].n == n) {
         NsState *st = inst[i].st;
         double h = st->hfix;
         if (st->cfl_dx > 0) {
@@ -164,6 +135,22 @@ __global__ void kb_set_h(const BInst *__restrict__ inst, int count) {
         st->t += h;
         st->umax = 0u;
     }
+}
+
+// The pass kernels of one size class.
+struct BClassFns {
+    int n;
+    void (*p1)(const BInst *, const BItem *, int, int);
+    void (*y)(const BInst *, const BItem *, int, int, int);
+    void (*p3)(const BInst *, const BItem *, int, int);
+    void (*p5)(const BInst *, const BItem *, int, int);
+};
+static BClassFns class_fns(int n) {
+#define TK_FNS(N) \
+    if (n == N) return {N, &kb_p1<N>, &kb_y<N>, &kb_p3<N>, &kb_p5<N>};
+    TK_BATCH_SIZES(TK_FNS)
+#undef TK_FNS
+    return {0, nullptr, nullptr, nullptr, nullptr};
 }
 
 // Tiles per instance of each pass.
@@ -204,9 +191,11 @@ struct tk_nsb_s {
     BInst *dinst = nullptr;
     std::vector<NsState> hstate;
     NsState *dstate = nullptr;
-    // work lists: 0 = P5, 1 = Y over 6 fields, 2 = Z lines, 3 = Y over 3 fields, 4 = P1
-    BItem *items[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    int nitems[5] = {0, 0, 0, 0, 0};
+    // per size class c: work lists 0 = P5, 1 = Y over 6 fields, 2 = Z lines, 3 = Y over 3
+    // fields, 4 = P1, at items[c][list]
+    std::vector<int> cls_n;
+    std::vector<std::array<BItem *, 5>> items;
+    std::vector<std::array<int, 5>> nitems;
     std::vector<void *> bufs;
     double *dscratch = nullptr;
     hipGraph_t graph = nullptr;
@@ -218,38 +207,72 @@ static void nsb_free(tk_nsb_s *b) {
     if (b->gexec) hipGraphExecDestroy(b->gexec);
     if (b->graph) hipGraphDestroy(b->graph);
     for (void *p : b->bufs) hipFree(p);
-    for (auto &it : b->items)
-        if (it) hipFree(it);
+    for (auto &c : b->items)
+        for (BItem *it : c)
+            if (it) hipFree(it);
     if (b->dinst) hipFree(b->dinst);
     if (b->dstate) hipFree(b->dstate);
     if (b->dscratch) hipFree(b->dscratch);
     delete b;
 }
 
+// One IF-RK2 step of every member as one graph: each size class runs its own chain of
+// passes (P1, Y, P3, step size, Y, P5, twice) on a stream of its own, forked from and
+// joined to the capture stream, so the classes' kernels overlap on the GPU.
 static tk_status nsb_capture(tk_nsb_s *b) {
+    const int nc = (int)b->cls_n.size();
     hipStream_t cs;
     TK_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    TK_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, b->nitems[list])); };
-    for (int stage = 0; stage < 2; ++stage) {
-        hipLaunchKernelGGL(kb_p1, dim3(g(4)), dim3(BNT), 0, cs, b->dinst, b->items[4], b->nitems[4], stage);
-        hipLaunchKernelGGL(kb_y, dim3(g(1)), dim3(BNT), 0, cs, b->dinst, b->items[1], b->nitems[1], 6, 1);
-        hipLaunchKernelGGL(kb_p3, dim3(g(2)), dim3(BNT), 0, cs, b->dinst, b->items[2], b->nitems[2], stage == 0);
-        if (stage == 0)
-            hipLaunchKernelGGL(kb_set_h, dim3(cdiv(b->count, 64)), dim3(64), 0, cs, b->dinst, b->count);
-        hipLaunchKernelGGL(kb_y, dim3(g(3)), dim3(BNT), 0, cs, b->dinst, b->items[3], b->nitems[3], 3, 0);
-        hipLaunchKernelGGL(kb_p5, dim3(g(0)), dim3(BNT), 0, cs, b->dinst, b->items[0], b->nitems[0],
-                           stage == 0 ? (int)RK2_S1 : (int)RK2_S2);
+    std::vector<hipStream_t> ss(nc, nullptr);
+    std::vector<hipEvent_t> ev(nc + 1, nullptr);
+    tk_status st = TK_OK;
+    auto cleanup = [&] {
+        for (auto q : ss)
+            if (q) hipStreamDestroy(q);
+        for (auto e : ev)
+            if (e) hipEventDestroy(e);
+        hipStreamDestroy(cs);
+    };
+    for (int c = 0; c < nc; ++c)
+        if (hipStreamCreateWithFlags(&ss[c], hipStreamNonBlocking) != hipSuccess) st = TK_EHIP;
+    for (int c = 0; c <= nc; ++c)
+        if (hipEventCreateWithFlags(&ev[c], hipEventDisableTiming) != hipSuccess) st = TK_EHIP;
+    if (st != TK_OK) {
+        cleanup();
+        return fail(TK_EHIP, "ensemble stream setup failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipEventRecord(ev[nc], cs);
+    for (int c = 0; c < nc && e == hipSuccess; ++c) {
+        hipStream_t q = ss[c];
+        e = hipStreamWaitEvent(q, ev[nc], 0);
+        if (e != hipSuccess) break;
+        const BClassFns f = class_fns(b->cls_n[c]);
+        const auto &it = b->items[c];
+        const auto &ni = b->nitems[c];
+        auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, ni[list])); };
+        for (int stage = 0; stage < 2; ++stage) {
+            hipLaunchKernelGGL(f.p1, dim3(g(4)), dim3(BNT), 0, q, b->dinst, it[4], ni[4], stage);
+            hipLaunchKernelGGL(f.y, dim3(g(1)), dim3(BNT), 0, q, b->dinst, it[1], ni[1], 6, 1);
+            hipLaunchKernelGGL(f.p3, dim3(g(2)), dim3(BNT), 0, q, b->dinst, it[2], ni[2], stage == 0);
+            if (stage == 0)
+                hipLaunchKernelGGL(kb_set_h, dim3(cdiv(b->count, 64)), dim3(64), 0, q, b->dinst, b->count, f.n);
+            hipLaunchKernelGGL(f.y, dim3(g(3)), dim3(BNT), 0, q, b->dinst, it[3], ni[3], 3, 0);
+            hipLaunchKernelGGL(f.p5, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0],
+                               stage == 0 ? (int)RK2_S1 : (int)RK2_S2);
+        }
+        e = hipEventRecord(ev[c], q);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[c], 0);
     }
     hipGraph_t gr = nullptr;
-    hipError_t le = hipGetLastError();
-    hipError_t e = hipStreamEndCapture(cs, &gr);
-    hipStreamDestroy(cs);
-    if (le != hipSuccess) {
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(cs, &gr);
+    cleanup();
+    if (e != hipSuccess || le != hipSuccess) {
         if (gr) hipGraphDestroy(gr);
-        return fail(TK_EHIP, "ensemble kernel launch failed: %s", hipGetErrorString(le));
+        return fail(TK_EHIP, "ensemble graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : le));
     }
-    if (e != hipSuccess) return fail(TK_EHIP, "ensemble graph capture failed: %s", hipGetErrorString(e));
+    if (ee != hipSuccess) return fail(TK_EHIP, "ensemble graph capture failed: %s", hipGetErrorString(ee));
     e = hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         hipGraphDestroy(gr);
@@ -326,26 +349,33 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
         return fail(TK_ENOMEM, "ensemble tables allocation failed");
     }
     for (int i = 0; i < count; ++i) b->hinst[i].st = b->dstate + i;
-    // work lists, largest grids first
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
-    for (int list = 0; list < 5; ++list) {
-        std::vector<BItem> v;
-        for (int i : order) {
-            const BInst &d = b->hinst[i];
-            long nt = list == 0 ? tiles_x(d.n, d.K, d.KZC)
-                      : list == 1 ? tiles_y(d.n, d.KZP, 6)
-                      : list == 2 ? tiles_z(d.n)
-                      : list == 3 ? tiles_y(d.n, d.KZP, 3)
-                                  : tiles_x(d.n, d.K, d.KZP);
-            for (long t = 0; t < nt; ++t) v.push_back({i, (int)t});
-        }
-        b->nitems[list] = (int)v.size();
-        if (hipMalloc((void **)&b->items[list], sizeof(BItem) * v.size()) != hipSuccess ||
-            hipMemcpy(b->items[list], v.data(), sizeof(BItem) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            nsb_free(b);
-            return fail(TK_ENOMEM, "work list upload failed");
+    // size classes, largest grids first; per class its work lists
+    std::vector<int> sizes(n, n + count);
+    std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    b->cls_n = sizes;
+    b->items.assign(sizes.size(), {nullptr, nullptr, nullptr, nullptr, nullptr});
+    b->nitems.assign(sizes.size(), {0, 0, 0, 0, 0});
+    for (size_t c = 0; c < sizes.size(); ++c) {
+        for (int list = 0; list < 5; ++list) {
+            std::vector<BItem> v;
+            for (int i = 0; i < count; ++i) {
+                const BInst &d = b->hinst[i];
+                if (d.n != sizes[c]) continue;
+                long nt = list == 0 ? tiles_x(d.n, d.K, d.KZC)
+                          : list == 1 ? tiles_y(d.n, d.KZP, 6)
+                          : list == 2 ? tiles_z(d.n)
+                          : list == 3 ? tiles_y(d.n, d.KZP, 3)
+                                      : tiles_x(d.n, d.K, d.KZP);
+                for (long t = 0; t < nt; ++t) v.push_back({i, (int)t});
+            }
+            b->nitems[c][list] = (int)v.size();
+            if (hipMalloc((void **)&b->items[c][list], sizeof(BItem) * v.size()) != hipSuccess ||
+                hipMemcpy(b->items[c][list], v.data(), sizeof(BItem) * v.size(), hipMemcpyHostToDevice) !=
+                    hipSuccess) {
+                nsb_free(b);
+                return fail(TK_ENOMEM, "work list upload failed");
+            }
         }
     }
     tk_status st = nsb_capture(b);
