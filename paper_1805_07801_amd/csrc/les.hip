@@ -38,35 +38,43 @@ __device__ __forceinline__ void load_weights(float *w, const uint16_t *__restric
     __syncthreads();
 }
 
-// Point p: h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), y = W3 h2 + b3, one point per thread,
-// weights broadcast from LDS.
-__global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
+// Parameter i of the BF16 set, read as a 32-bit word holding parameters 2k, 2k+1 (little
+// endian): with i uniform over the wavefront the read is a scalar load and the weight a
+// scalar operand of the FMA, so the products need no LDS traffic at all.
+__device__ __forceinline__ float wparam(const uint32_t *__restrict__ w32, int i) {
+    const uint32_t u = w32[i >> 1];
+    return __uint_as_float((i & 1) ? (u & 0xffff0000u) : (u << 16));
+}
+
+// Point p: h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), y = W3 h2 + b3, one point per thread
+// (no loop over points: the weight loads would be hoisted out of it into more scalar
+// registers than there are).
+__global__ __launch_bounds__(MB) void k_mlp_fwd(const uint32_t *__restrict__ w32, const float *__restrict__ x9,
                                                float *__restrict__ y6, long M, float in_inv, float out_scale) {
-    __shared__ float w[NP];
-    load_weights(w, wb);
-    for (long p = (long)blockIdx.x * MB + threadIdx.x; p < M; p += (long)gridDim.x * MB) {
+    const long p = (long)blockIdx.x * MB + threadIdx.x;
+    if (p < M) {
         float x[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) x[c] = x9[c * M + p] * in_inv;
         float h1[64];
 #pragma unroll
         for (int o = 0; o < 64; ++o) {
-            float a = w[OB1 + o];
+            float a = wparam(w32, OB1 + o);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) a = fmaf(w[OW1 + o * 9 + c], x[c], a);
+            for (int c = 0; c < 9; ++c) a = fmaf(wparam(w32, OW1 + o * 9 + c), x[c], a);
             h1[o] = gelu(a);
         }
         float y[6];
 #pragma unroll
-        for (int o = 0; o < 6; ++o) y[o] = w[OB3 + o];
-#pragma unroll 4
+        for (int o = 0; o < 6; ++o) y[o] = wparam(w32, OB3 + o);
+#pragma unroll 2
         for (int o = 0; o < 64; ++o) {
-            float a = w[OB2 + o];
+            float a = wparam(w32, OB2 + o);
 #pragma unroll
-            for (int i = 0; i < 64; ++i) a = fmaf(w[OW2 + o * 64 + i], h1[i], a);
+            for (int i = 0; i < 64; ++i) a = fmaf(wparam(w32, OW2 + o * 64 + i), h1[i], a);
             const float h2 = gelu(a);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) y[q] = fmaf(w[OW3 + q * 64 + o], h2, y[q]);
+            for (int q = 0; q < 6; ++q) y[q] = fmaf(wparam(w32, OW3 + q * 64 + o), h2, y[q]);
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) y6[q * M + p] = y[q] * out_scale;
@@ -401,8 +409,10 @@ static tk_status mlp_check(const tk_mlp *w) {
 }
 
 tk_status mlp_forward_run(const tk_mlp *w, const float *x9, float *y6, long M, hipStream_t s) {
-    const unsigned nb = (unsigned)std::min<long>(4096, std::max<long>(1, (M + MB - 1) / MB));
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(MB), 0, s, w->w, x9, y6, M, 1.0f / w->in_scale, w->out_scale);
+    if ((M + MB - 1) / MB > 0x7fffffffL) return fail(TK_EINVAL, "too many points (%ld)", M);
+    const unsigned nb = (unsigned)std::max<long>(1, (M + MB - 1) / MB);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(MB), 0, s, (const uint32_t *)w->w, x9, y6, M, 1.0f / w->in_scale,
+                       w->out_scale);
     return launch_check("network forward");
 }
 
