@@ -145,3 +145,29 @@ def test_persistent_candidates_full_rounds_and_tail(tk, L):
     finally:
         tk.tune_clear()
 
+
+
+def test_two_1024_members_split_per_plane(tk):
+    """Two 1024^3 members in one plan: the X pass's per-thread offsets would exceed 32 bits
+    across the members, so it runs once per member; every member's transform must equal the
+    single-member plan's, bit for bit, both directions."""
+    import torch
+    n = 1024
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((2, n, n, n), generator=g, device="cuda", dtype=torch.float32)
+    p2 = tk.FFT3D(n, batch=2, dtype=torch.float32)
+    X2 = p2.r2c(x)
+    p1 = tk.FFT3D(n, batch=1, dtype=torch.float32)
+    for b in range(2):
+        X1 = p1.r2c(x[b:b + 1].contiguous())
+        assert torch.equal(X1, X2[b:b + 1]), b
+        del X1
+    y2 = p2.c2r(X2)
+    for b in range(2):
+        y1 = p1.c2r(X2[b:b + 1].contiguous())
+        assert torch.equal(y1, y2[b:b + 1]), b
+        del y1
+    err = (torch.linalg.vector_norm((y2 - x).double()) / torch.linalg.vector_norm(x.double())).item()
+    assert err <= TOL["f32"]
+    p1.close()
+    p2.close()
