@@ -81,7 +81,7 @@ def les_rate(tk, torch, steps=50):
     return out
 
 
-def time_pairs(tk, torch, n, steps, warmup, seed=0):
+def time_pairs(tk, torch, n, steps, warmup, seed=0, repeats=False):
     import numpy as np
     import synth
     f = synth.gaussian_field((n, n, n), seed)
@@ -107,6 +107,16 @@ def time_pairs(tk, torch, n, steps, warmup, seed=0):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     pt = plan.pass_times()
+    # four more timed runs of the same K pairs, for the spread (the first run is `value`)
+    reps = [ms]
+    for _ in range(4 if repeats else 0):
+        t0.record(stream)
+        for _ in range(steps):
+            plan.r2c(x, X)
+            plan.c2r(X, y)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(t0.elapsed_time(t1) / steps)
     names = ["z_r2c", "y_fwd", "x_fwd", "x_inv", "y_inv", "z_c2r"]
     passes = dict(zip(names, pt))
     desc = {p: plan.describe(p) for p in range(3)}
@@ -114,7 +124,7 @@ def time_pairs(tk, torch, n, steps, warmup, seed=0):
     plan.close()
     del x, X, y
     torch.cuda.empty_cache()
-    return ms, passes, desc, err
+    return ms, passes, desc, err, reps
 
 
 def kernel_names(desc, n):
@@ -275,7 +285,7 @@ def main():
         for nn in ((512,) if args.no_1024 else (512, 1024)):
             tk.autotune(nn, iters=3)
     copy_gbps = copy_bandwidth(torch)
-    ms, passes, desc, err = time_pairs(tk, torch, n, args.steps, args.warmup)
+    ms, passes, desc, err, reps = time_pairs(tk, torch, n, args.steps, args.warmup, repeats=True)
     value = (2 * R + 10 * C) / (ms * 1e-3) / 1e9
     kname, roof = roofline(n, passes, kernel_names(desc, n))
     roof["traffic"] = traffic_from_profile(kname)
@@ -301,6 +311,8 @@ def main():
         "compulsory_GBps": round(2 * (R + C) / (ms * 1e-3) / 1e9, 1),
         "gflops_paper_convention": round(pair_flops(n) / (ms * 1e-3) / 1e9, 1),
         "roundtrip_rel_l2": err,
+        "pair_ms_repeats": [round(r, 4) for r in reps],
+        "pair_ms_median_of_5": round(sorted(reps)[len(reps) // 2], 4),
         "passes_ms": {k: round(v, 4) for k, v in passes.items()},
         "passes_GBps": {k: round(pb[k] / (passes[k] * 1e-3) / 1e9, 1) for k in passes if passes[k] > 0},
         "tiles": desc,
@@ -310,7 +322,7 @@ def main():
         n2 = 1024
         R2, C2 = field_bytes(n2)
         k2 = max(5, args.steps // 5)
-        ms2, passes2, desc2, err2 = time_pairs(tk, torch, n2, k2, max(2, args.warmup // 5))
+        ms2, passes2, desc2, err2, _ = time_pairs(tk, torch, n2, k2, max(2, args.warmup // 5))
         pb2 = pass_bytes(n2)
         out["fft1024"] = {
             "ms_per_pair": round(ms2, 3),

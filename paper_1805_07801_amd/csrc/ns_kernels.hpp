@@ -348,9 +348,7 @@ struct P5Args {
     int mode;
 };
 
-// PRE: the stage combine's operands (u, and aux where the mode reads it) are loaded with
-// the input, before the transforms, instead of after them.
-template <typename T, int L, int E, int W, bool PRE = false>
+template <typename T, int L, int E, int W>
 __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3, V2<T> *u,
                                            V2<T> *aux, V2<T> *ust, V2<T> *out, const NsState *__restrict__ st,
                                            double nu, int mode, int K, int KZC, long tile, V2<T> *lds,
@@ -383,22 +381,6 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
 #pragma unroll
         for (int i = 0; i < E; ++i)
             cf[f][i] = valid ? *at_bytes(c3 + f * FSc + (long)(i * TPL) * RSc, loc) : mk<T>(0, 0);
-    }
-    constexpr int PE = PRE ? E : 1;
-    C pu[3][PE], pa[3][PE];
-    if constexpr (PRE) {
-        const bool need_u = valid && mode != NS_RHS;
-        const bool need_aux = valid && (mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const bool kept = row_kept(jt + i * TPL, L, K);
-                const long ro = f * FS + (long)(i * TPL) * RS;
-                pu[f][i] = (need_u && kept) ? *at_bytes(u + ro, lo) : mk<T>(0, 0);
-                pa[f][i] = (need_aux && kept) ? *at_bytes(aux + ro, lo) : mk<T>(0, 0);
-            }
-        }
     }
     // unrolled over the fields: a run-time field index into cf would put it in scratch
 #pragma unroll
@@ -440,8 +422,7 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const T th = (T)h;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const C uu = PRE ? pu[f][PRE ? i : 0] : *at(u, f);
-                const C ax = PRE ? pa[f][PRE ? i : 0] : mk<T>(0, 0);
+                const C uu = *at(u, f);
                 const C n = nn[f];
                 switch (mode) {
                 case RK2_S1:
@@ -449,22 +430,22 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
                     *at(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
                 case RK2_S2:
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(PRE ? ax : *at(aux, f), e1), n), (T)0.5 * th));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*at(aux, f), e1), n), (T)0.5 * th));
                     break;
                 case RK4_S1:
                     *at(aux, f) = cscale(n, e1);
                     *at(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
                 case RK4_S2:
-                    *at(aux, f) = cadd(PRE ? ax : *at(aux, f), cscale(n, (T)2 * e2));
+                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
                     *at(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
-                    *at(aux, f) = cadd(PRE ? ax : *at(aux, f), cscale(n, (T)2 * e2));
+                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
                     *at(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(PRE ? ax : *at(aux, f), n), th / (T)6));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*at(aux, f), n), th / (T)6));
                     break;
                 }
             }
@@ -472,7 +453,7 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
     }
 }
 
-template <typename T, int L, int E, int W, bool PRE = false>
+template <typename T, int L, int E, int W>
 __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3,
                                                        V2<T> *u, V2<T> *aux, V2<T> *ust, V2<T> *out,
                                                        const NsState *__restrict__ st, double nu, int mode, int K,
@@ -482,8 +463,8 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ 
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
     __syncthreads();
-    ns_p5_tile<T, L, E, W, PRE>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x),
-                                lds, tw);
+    ns_p5_tile<T, L, E, W>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds,
+                           tw);
 }
 
 // ---- P5 of the Boussinesq (RBC) right-hand side ----------------------------------------------------
@@ -693,10 +674,10 @@ template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long 
     hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
                        (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, part);
 }
-template <typename T, int N, int E, int W, bool PRE = false>
+template <typename T, int N, int E, int W>
 void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
     const long ncols = (long)(2 * K + 1) * KZC;
-    hipLaunchKernelGGL((k_ns_p5<T, N, E, W, PRE>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
+    hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
                        (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, (V2<T> *)a.ust, (V2<T> *)a.out, a.st,
                        a.nu, a.mode, K, KZC, (const V2<T> *)tw);
 }
