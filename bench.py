@@ -258,6 +258,26 @@ def ns_steps_per_s(tk, torch, n, steps, warmup):
     return steps / dt, e
 
 
+def tg32_steps_per_s(tk, torch, steps=200):
+    """Steps/s of the 32^3 FP64 Taylor-Green configuration (nu 0.01, fixed dt 0.01, IF-RK2):
+    launch/latency-bound, one graph launch per step."""
+    import synth
+    from paper_1805_07801_amd import FFT3D
+    n = 32
+    plan = FFT3D(n, batch=3, dtype=torch.float64)
+    u = plan.r2c(torch.from_numpy(synth.taylor_green(n)).cuda())
+    plan.close()
+    ns = tk.NS(n, dtype=torch.float64, nu=0.01)
+    ns.step(u, 0.01, 10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ns.step(u, 0.01, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ns.close()
+    return steps / dt
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +356,7 @@ def main():
         sps, e = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 2), 2)
         out["ns512_rk2_steps_per_s"] = round(sps, 2)
         out["ns512_energy_after"] = e
+        out["tg32_fp64_rk2_steps_per_s"] = round(tg32_steps_per_s(tk, torch), 1)
     if not args.no_extra:
         out.update(ensemble_rate(tk, torch))
         out.update(les_rate(tk, torch))

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BNT) void kb_p1(const BInst *__restrict__ inst, con
         __syncthreads();
         load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
         __syncthreads();
-        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, d.KZC, w.tile, smem + N, tw);
+        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, stage2, w.tile, smem + N, tw);
     }
 }
 
@@ -154,7 +154,7 @@ static BClassFns class_fns(int n) {
 }
 
 // Tiles per instance of each pass.
-// ncols_per_ky: KZC for P5 (kept columns), KZP for P1 (transit columns).
+// ncols_per_ky: the KZP transit columns of each kept ky row (P1 and P5).
 static long tiles_x(int n, int K, int ncols_per_ky) {
     long W = 0;
 #define TK_W(N) if (n == N) W = BCfg<N>::W;
@@ -362,7 +362,7 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
             for (int i = 0; i < count; ++i) {
                 const BInst &d = b->hinst[i];
                 if (d.n != sizes[c]) continue;
-                long nt = list == 0 ? tiles_x(d.n, d.K, d.KZC)
+                long nt = list == 0 ? tiles_x(d.n, d.K, d.KZP)
                           : list == 1 ? tiles_y(d.n, d.KZP, 6)
                           : list == 2 ? tiles_z(d.n)
                           : list == 3 ? tiles_y(d.n, d.KZP, 3)

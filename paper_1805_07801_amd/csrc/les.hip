@@ -269,12 +269,14 @@ __global__ void k_count_nonfinite(const uint16_t *__restrict__ wb, int n, int *_
 }
 
 // ---- spectral helpers ---------------------------------------------------------------------------------
-// g[3 i + j] = i k_j u^_i (Nyquist derivative taken as zero), 9 fields.  Only modes with
-// |kx|, |ky|, kz <= K are read (the others are zero in a 2/3-masked state, and the
-// solver's stage buffers leave them unwritten).
-__global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g, int N, int K) {
+// g[3 i + j] = i k_j u^_i (Nyquist derivative taken as zero), 9 fields in the state layout.
+// Only modes with |kx|, |ky|, kz <= K are read (the others are zero in a 2/3-masked state,
+// and the solver's stage buffers leave them unwritten); u has rows of `rowlen` complex
+// values per (x, y): N/2+1 for a state, the transit length for a stage buffer.
+__global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g, int N, int K, int rowlen) {
     const int NZH = N / 2 + 1;
     const long FS = (long)N * N * NZH;
+    const long FSu = (long)N * N * rowlen;
     for (long m = (long)blockIdx.x * blockDim.x + threadIdx.x; m < FS; m += (long)gridDim.x * blockDim.x) {
         const int kz0 = (int)(m % NZH);
         const long xy = m / NZH;
@@ -284,7 +286,7 @@ __global__ void k_grad_spec(const float2 *__restrict__ u, float2 *__restrict__ g
         const bool kept = abs(x < N / 2 ? x : x - N) <= K && abs(y < N / 2 ? y : y - N) <= K && kz0 <= K;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const float2 a = kept ? u[i * FS + m] : make_float2(0.f, 0.f);
+            const float2 a = kept ? u[i * FSu + xy * rowlen + kz0] : make_float2(0.f, 0.f);
 #pragma unroll
             for (int j = 0; j < 3; ++j) g[(3 * i + j) * FS + m] = make_float2(-a.y * k[j], a.x * k[j]);
         }
@@ -466,14 +468,16 @@ static tk_status les_work_alloc(tk_ns_t p) {
     return TK_OK;
 }
 
-// add3 = -i k_j tau^_ij with tau = out_scale f(grad(u) / in_scale) evaluated on the grid.
-static tk_status les_closure(tk_ns_t p, const tk_mlp *w, const void *u, hipStream_t s) {
+// add3 = -i k_j tau^_ij with tau = out_scale f(grad(u) / in_scale) evaluated on the grid;
+// u_transit: u is the stage buffer (transit layout) rather than the state.
+static tk_status les_closure(tk_ns_t p, const tk_mlp *w, const void *u, int u_transit, hipStream_t s) {
     const NsGrid &g = p->g;
     const int n = g.n;
     const long FS = (long)n * n * (n / 2 + 1);
     const long M = (long)n * n * n;
     LesWork &L = p->les;
-    hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)u, (float2 *)L.gsp, n, g.K);
+    hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FS)), dim3(256), 0, s, (const float2 *)u, (float2 *)L.gsp, n, g.K,
+                       u_transit ? g.KZP : n / 2 + 1);
     TK_TRY(launch_check("gradient spectra"));
     TK_TRY(fft_x_pass(g.ax, L.gsp, L.gsp, 9, 1, 1.0, s));
     TK_TRY(fft_y_pass(g.ax, L.gsp, L.gsp, 9, 1, s));
@@ -495,13 +499,13 @@ static tk_status les_steps(tk_ns_t p, const tk_mlp *w, void *u, int nsteps, hipS
     a.st = p->st;
     a.nu = p->cfg.nu;
     for (int k = 0; k < nsteps; ++k) {
-        if (w) TK_TRY(les_closure(p, w, u, s));
+        if (w) TK_TRY(les_closure(p, w, u, 0, s));
         a.add3 = w ? p->les.add3 : nullptr;
         a.mode = RK2_S1;
         TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
-        if (w) TK_TRY(les_closure(p, w, p->ust, s));
+        if (w) TK_TRY(les_closure(p, w, p->ust, 1, s));
         a.mode = RK2_S2;
-        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s, 1));
     }
     return TK_OK;
 }
@@ -670,7 +674,7 @@ extern "C" tk_status les_filter_dns(const void *uhat_dns, int n_dns, int n_les, 
         if ((st = launch_check("truncate u")) != TK_OK) break;
         if (ubar_hat) TK_HIP_CHECK(hipMemcpyAsync(ubar_hat, ubh, sizeof(float2) * 3 * FL, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_grad_spec, dim3(ew_blocks(FL)), dim3(256), 0, s, (const float2 *)ubh, (float2 *)gsp,
-                           n_les, kc);
+                           n_les, kc, n_les / 2 + 1);
         if ((st = launch_check("gradient spectra")) != TK_OK) break;
         if ((st = fft_x_pass(B, gsp, gsp, 9, 1, 1.0, s)) != TK_OK) break;
         if ((st = fft_y_pass(B, gsp, gsp, 9, 1, s)) != TK_OK) break;

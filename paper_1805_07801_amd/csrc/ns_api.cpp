@@ -55,10 +55,10 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
 }
 
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s) {
+                      NsState *st_set, hipStream_t s, int uin_transit) {
     const int n = g.n;
     // P1: x-inverse of u^ and omega^ = i k x u^
-    g.nk->p1v[g.v1].fn(uin, w6, g.K, g.KZC, g.ax.twx, s);
+    g.nk->p1v[g.v1].fn(uin, w6, g.K, uin_transit, g.ax.twx, s);
     TK_TRY(launch_check("ns P1"));
     // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
     StridedArgs y2{w6, w6, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
@@ -181,13 +181,13 @@ static tk_status ns_one_step(tk_ns_s *p, void *u, hipStream_t s) {
         a.mode = RK2_S1;
         TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
         a.mode = RK2_S2;
-        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s, 1));
     } else {
         a.mode = RK4_S1;
         TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
         for (int m = RK4_S2; m <= RK4_S4; ++m) {
             a.mode = m;
-            TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s));
+            TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s, 1));
         }
     }
     return TK_OK;

@@ -30,11 +30,12 @@ struct NsGrid {
 tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
 
 // One right-hand side of input uin (3 fields) through P1..P5 with workspace w6 (6 fields);
-// P5 combines according to `mode` (see NsMode).  part != null (n^2 floats): P3 records
+// P5 combines according to `mode` (see NsMode); the stage buffers aux and ust are in the
+// transit layout (uin_transit = 1 when uin is ust).  part != null (n^2 floats): P3 records
 // max |u|_1 per workgroup and, when st_set != null, the step-size kernel reduces them
 // after P3.
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s);
+                      NsState *st_set, hipStream_t s, int uin_transit = 0);
 
 // Random solenoidal initial state from real noise [3][n][n][n] (see ns_init_random).
 tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, double energy, double *dscratch,

@@ -75,7 +75,8 @@ template <int N> constexpr int ns_kzp() {
 
 // Column of a P1 tile for thread (col, jt) = (tid % W, tid / W): column (ky, kz) of the
 // kept ky rows and the KZP transit columns; its input point i of field f at element
-// f FS + i TPL RS (uniform) + lo / sizeof(C) of the state, its output point at
+// f FSi + i TPL RSi (uniform) + lo / sizeof(C), where the input has rows of NZH (the
+// state) or, with cin, of KZP (a stage buffer in the transit layout); its output point at
 // f FSc + i TPL RSc + lo2 / sizeof(C) of the transit fields.
 struct P1Col {
     int ky, kz;
@@ -84,11 +85,12 @@ struct P1Col {
 };
 
 template <typename T, int L, int E, int W>
-__device__ __forceinline__ P1Col ns_p1_col(long tile, int K) {
+__device__ __forceinline__ P1Col ns_p1_col(long tile, int K, int cin) {
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
     constexpr int KZP = ns_kzp<N>();
-    constexpr long RS = (long)N * NZH;
+    const long rowi = cin ? KZP : NZH;
+    const long RSi = (long)N * rowi;
     constexpr long RSc = (long)N * KZP;
     const int col = threadIdx.x % W;
     const int jt = threadIdx.x / W;
@@ -104,19 +106,21 @@ __device__ __forceinline__ P1Col ns_p1_col(long tile, int K) {
         row = kyi <= K ? kyi : kyi + N - 2 * K - 1;
         c.ky = wave_k((int)row, N);
     }
-    c.lo = (unsigned)((row * NZH + c.kz + (long)jt * RS) * (long)sizeof(V2<T>));
+    c.lo = (unsigned)((row * rowi + c.kz + (long)jt * RSi) * (long)sizeof(V2<T>));
     c.lo2 = (unsigned)((row * KZP + c.kz + (long)jt * RSc) * (long)sizeof(V2<T>));
     return c;
 }
 
-// The kept x rows of the tile's 3 (RBC: 4) input fields.
+// The kept x rows of the tile's 3 (RBC: 4) input fields (rows of NZH, or KZP with cin).
 template <typename T, int L, int E, int W, bool RBC>
-__device__ __forceinline__ void ns_p1_load(const V2<T> *__restrict__ u, const P1Col &c, int K, V2<T> (&a0)[E],
-                                           V2<T> (&a1)[E], V2<T> (&a2)[E], V2<T> (&a3)[RBC ? E : 1]) {
+__device__ __forceinline__ void ns_p1_load(const V2<T> *__restrict__ u, const P1Col &c, int K, int cin,
+                                           V2<T> (&a0)[E], V2<T> (&a1)[E], V2<T> (&a2)[E],
+                                           V2<T> (&a3)[RBC ? E : 1]) {
     constexpr int N = L;
     constexpr int TPL = L / E;
-    constexpr long FS = (long)N * N * (N / 2 + 1);
-    constexpr long RS = (long)N * (N / 2 + 1);
+    const long rowi = cin ? ns_kzp<N>() : N / 2 + 1;
+    const long FS = (long)N * N * rowi;
+    const long RS = (long)N * rowi;
     const int jt = threadIdx.x / W;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -173,25 +177,27 @@ __device__ __forceinline__ void ns_p1_body(const V2<T> (&a0)[E], const V2<T> (&a
     }
 }
 
+// cin: the input u is a stage buffer in the transit layout (rows of KZP) instead of a
+// state with rows of N/2+1.
 template <typename T, int L, int E, int W, bool RBC = false>
-__device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int KZC,
+__device__ __forceinline__ void ns_p1_tile(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K, int cin,
                                            long tile, V2<T> *lds, const V2<T> *tw, T ka = (T)1) {
     using C = V2<T>;
-    const P1Col c = ns_p1_col<T, L, E, W>(tile, K);
+    const P1Col c = ns_p1_col<T, L, E, W>(tile, K, cin);
     C a0[E], a1[E], a2[E], a3[RBC ? E : 1];
-    ns_p1_load<T, L, E, W, RBC>(u, c, K, a0, a1, a2, a3);
+    ns_p1_load<T, L, E, W, RBC>(u, c, K, cin, a0, a1, a2, a3);
     ns_p1_body<T, L, E, W, RBC>(a0, a1, a2, a3, w6, c, lds, tw, ka);
 }
 
 template <typename T, int L, int E, int W, bool RBC = false>
 __global__ __launch_bounds__(W *(L / E)) void k_ns_p1(const V2<T> *__restrict__ u, V2<T> *__restrict__ w6, int K,
-                                                       int KZC, const V2<T> *__restrict__ twg, T ka) {
+                                                       int cin, const V2<T> *__restrict__ twg, T ka) {
     using C = V2<T>;
     __shared__ C lds[L * (W + 1)];
     __shared__ C tw[L];
     load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
     __syncthreads();
-    ns_p1_tile<T, L, E, W, RBC>(u, w6, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds, tw, ka);
+    ns_p1_tile<T, L, E, W, RBC>(u, w6, K, cin, xcd_tile(blockIdx.x, gridDim.x), lds, tw, ka);
 }
 
 // ---- P3: fused Z pass ------------------------------------------------------------------------------
@@ -337,11 +343,11 @@ __global__ __launch_bounds__(LPW *(L / E)) void k_ns_p3(V2<T> *w6, long nlines, 
 
 // ---- P5: X-forward with projection and the Runge-Kutta stage combine --------------------------------
 struct P5Args {
-    const void *c3;    // 3 fields after P4
+    const void *c3;    // 3 fields after P4 (transit layout)
     const void *add3;  // optional extra term added before masking/projection (spectral, scaled), or null
     void *u;           // state (read; written by RK2_S2 / RK4_S4)
-    void *aux;         // RK2: N^n; RK4: accumulator
-    void *ust;         // stage input written by the first stages
+    void *aux;         // RK2: N^n; RK4: accumulator (transit layout)
+    void *ust;         // stage input written by the first stages (transit layout)
     void *out;         // NS_RHS output
     const NsState *st;
     double nu;
@@ -363,18 +369,28 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
     const int tid = threadIdx.x;
     const int col = tid % W;
     const int jt = tid / W;
-    const long ncols = (long)(2 * K + 1) * KZC;
-    const long cc = tile * W + col;
-    const bool valid = cc < ncols;
-    int ky = 0, kz = 0;
-    const long j = valid ? kept_col(cc, N, K, KZC, NZH, &ky, &kz) : 0;
-    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane);
-    // in the transit fields c3 at f FSc + i TPL RSc + loc / sizeof(C)
+    // columns: the kept ky rows times the KZP transit columns (the padding columns, kz > K,
+    // are masked modes: N = 0 there, so the stage buffers' rows are written whole)
     constexpr int KZP = ns_kzp<N>();
     constexpr long FSc = (long)N * N * KZP;
     constexpr long RSc = (long)N * KZP;
-    const unsigned lo = (unsigned)((j + (long)jt * RS) * (long)sizeof(C));
-    const unsigned loc = (unsigned)(((j / NZH) * KZP + kz + (long)jt * RSc) * (long)sizeof(C));
+    const long ncols = (long)(2 * K + 1) * KZP;
+    const long cc = tile * W + col;
+    const bool valid = cc < ncols;
+    int ky = 0, kz = 0;
+    long row = 0;
+    if (valid) {
+        const long kyi = cc / KZP;
+        kz = (int)(cc - kyi * KZP);
+        row = kyi <= K ? kyi : kyi + N - 2 * K - 1;
+        ky = wave_k((int)row, N);
+    }
+    const bool kz_kept = kz <= K;
+    // point i of field f at element f FS + i TPL RS (uniform) + lo / sizeof(C) (per lane) in
+    // the state-layout fields (u, add3, out); at f FSc + i TPL RSc + loc / sizeof(C) in the
+    // transit-layout fields (c3, aux, ust)
+    const unsigned lo = (unsigned)((row * NZH + kz + (long)jt * RS) * (long)sizeof(C));
+    const unsigned loc = (unsigned)((row * KZP + kz + (long)jt * RSc) * (long)sizeof(C));
     C cf[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -394,14 +410,15 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             if (!row_kept(r, L, K)) continue;
             const int kx = wave_k(r, N);
             auto at = [&](auto *b, int f) { return at_bytes(b + f * FS + (long)(i * TPL) * RS, lo); };
+            auto atc = [&](auto *b, int f) { return at_bytes(b + f * FSc + (long)(i * TPL) * RSc, loc); };
             C n0 = cscale(cf[0][i], scale), n1 = cscale(cf[1][i], scale), n2 = cscale(cf[2][i], scale);
-            if (add3) {
+            if (add3 && kz_kept) {
                 n0 = cadd(n0, *at(add3, 0));
                 n1 = cadd(n1, *at(add3, 1));
                 n2 = cadd(n2, *at(add3, 2));
             }
             const T k2 = (T)(kx * kx + ky * ky + kz * kz);
-            if (k2 > 0) {
+            if (k2 > 0 && kz_kept) {
                 const T ik2 = (T)1 / k2;
                 const C kd = cadd(cadd(cscale(n0, (T)kx), cscale(n1, (T)ky)), cscale(n2, (T)kz));
                 n0 = csub(n0, cscale(kd, (T)kx * ik2));
@@ -426,26 +443,26 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
                 const C n = nn[f];
                 switch (mode) {
                 case RK2_S1:
-                    *at(aux, f) = n;
-                    *at(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
+                    *atc(aux, f) = n;
+                    *atc(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
                 case RK2_S2:
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*at(aux, f), e1), n), (T)0.5 * th));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*atc(aux, f), e1), n), (T)0.5 * th));
                     break;
                 case RK4_S1:
-                    *at(aux, f) = cscale(n, e1);
-                    *at(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
+                    *atc(aux, f) = cscale(n, e1);
+                    *atc(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
                 case RK4_S2:
-                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
-                    *at(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
+                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, (T)2 * e2));
+                    *atc(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
-                    *at(aux, f) = cadd(*at(aux, f), cscale(n, (T)2 * e2));
-                    *at(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
+                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, (T)2 * e2));
+                    *atc(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*at(aux, f), n), th / (T)6));
+                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*atc(aux, f), n), th / (T)6));
                     break;
                 }
             }
@@ -638,7 +655,8 @@ constexpr int ns_z_LPW(int N) {
 
 // Tile-shape variants of P1, P3 and P5 (the autotuner picks one per grid size and dtype;
 // variant 0 is the default above).  P1 / P5: a = W columns; P3: a = LPW lines.
-using NsP1Fn = void (*)(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s);
+// P1: cin = 1 when u is a stage buffer in the transit layout
+using NsP1Fn = void (*)(const void *u, void *w6, int K, int cin, const void *tw, hipStream_t s);
 using NsP3Fn = void (*)(void *w6, long nlines, int KZC, const void *tw, float *part, hipStream_t s);
 using NsP5Fn = void (*)(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s);
 template <typename F> struct NsVar {
@@ -664,10 +682,10 @@ struct NsKernels {
 const std::vector<NsKernels> &ns_kernels();
 
 template <typename T, int N, int E, int W>
-void launch_ns_p1(const void *u, void *w6, int K, int KZC, const void *tw, hipStream_t s) {
+void launch_ns_p1(const void *u, void *w6, int K, int cin, const void *tw, hipStream_t s) {
     const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
     hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)u,
-                       (V2<T> *)w6, K, KZC, (const V2<T> *)tw, (T)1);
+                       (V2<T> *)w6, K, cin, (const V2<T> *)tw, (T)1);
 }
 template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long nlines, int KZC, const void *tw,
                                                                  float *part, hipStream_t s) {
@@ -676,7 +694,7 @@ template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long 
 }
 template <typename T, int N, int E, int W>
 void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
-    const long ncols = (long)(2 * K + 1) * KZC;
+    const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
     hipLaunchKernelGGL((k_ns_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)a.c3,
                        (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, (V2<T> *)a.ust, (V2<T> *)a.out, a.st,
                        a.nu, a.mode, K, KZC, (const V2<T> *)tw);
@@ -733,9 +751,10 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     add_ns_p5_var<T, N, Ed, 1024 * Ed / N>(k);
     add_ns_z_var<T, N, default_E(L2) / 2>(k);
     k.p1r = [](const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s) {
+        // the convection solver keeps its stage buffers in the state layout
         const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
         hipLaunchKernelGGL((k_ns_p1<T, N, E, W, true>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
-                           (const V2<T> *)u, (V2<T> *)w7, K, KZC, (const V2<T> *)tw, (T)ka);
+                           (const V2<T> *)u, (V2<T> *)w7, K, 0, (const V2<T> *)tw, (T)ka);
     };
     k.p3r = [](void *w7, long nlines, int KZC, const void *tw, float *part, hipStream_t s) {
         hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW, true>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,

@@ -309,13 +309,13 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
         for (int i = 0; i < k->np1; ++i) {
             const auto &v = k->p1v[i];
             TK_HIP_CHECK(hipMemsetAsync(B.w6, 0, 6 * fb, s));
-            v.fn(B.u, B.w6, g.K, g.KZC, g.ax.twx, s);
+            v.fn(B.u, B.w6, g.K, 0, g.ax.twx, s);
             TK_TRY(launch_check("autotune P1"));
             if (i == 0) TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.w6, 6 * fb, hipMemcpyDeviceToDevice, s));
             bool ok = true;
             if (i > 0) TK_TRY(check(B.w6, B.ref, 12 * nf, &ok));
             float ms;
-            TK_TRY(time_it([&] { v.fn(B.u, B.w6, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
+            TK_TRY(time_it([&] { v.fn(B.u, B.w6, g.K, 0, g.ax.twx, s); }, iters, s, &ms));
             snprintf(line, sizeof(line), "pass p1 N=%d W=%d E=%d v=%d: %.4f ms %s\n", n, v.a, v.E, v.v, ms,
                      ok ? "ok" : "REJECTED");
             rep += line;
