@@ -162,6 +162,51 @@ template <int ES> __device__ __forceinline__ void exchange_sync() {
     else __syncthreads();
 }
 
+// Exchange between stage S and S + 1: leg m of butterfly j goes to position
+// (j - j mod NS) R + j mod NS + m NS, and the thread reads back its own points.
+template <typename T, int L, int E, int ES, int S, bool SPLIT>
+__device__ __forceinline__ void stage_exchange(V2<T> (&v)[E], V2<T> *d, int jt) {
+    constexpr RPlan P = make_rplan(L, E);
+    constexpr int R = P.r[S];
+    constexpr int NS = rplan_span(P, S);
+    constexpr int NB = E / R;
+    constexpr int TPL = L / E;
+    if constexpr (SPLIT) {
+        T *ds = reinterpret_cast<T *>(d);
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = jt + b * TPL;
+                const int k = j % NS;
+                const int base = (j - k) * R + k;
+#pragma unroll
+                for (int m = 0; m < R; ++m) ds[lds_at<ES>(base + m * NS)] = part ? v[b + m * NB].y : v[b + m * NB].x;
+            }
+            exchange_sync<ES>();
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                if (part) v[i].y = ds[lds_at<ES>(jt + i * TPL)];
+                else v[i].x = ds[lds_at<ES>(jt + i * TPL)];
+            }
+            exchange_sync<ES>();
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = jt + b * TPL;
+            const int k = j % NS;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
+        }
+        exchange_sync<ES>();
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
+        exchange_sync<ES>();
+    }
+}
+
 // ---- the transform -------------------------------------------------------------------------------
 // v[i] = x[jt + i TPL] on entry, X[jt + i TPL] on exit (forward DFT, unscaled).
 // d: this line's LDS (element e at d[lds_at<ES>(e)]), tw: LDS table with W_L^j at
@@ -207,41 +252,7 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
         dft_legs<R, NB>(v, b);
     }
     if constexpr (S + 1 < P.n) {
-        if constexpr (SPLIT) {
-            T *ds = reinterpret_cast<T *>(d);
-#pragma unroll
-            for (int part = 0; part < 2; ++part) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const int j = jt + b * TPL;
-                    const int k = j % NS;
-                    const int base = (j - k) * R + k;
-#pragma unroll
-                    for (int m = 0; m < R; ++m)
-                        ds[lds_at<ES>(base + m * NS)] = part ? v[b + m * NB].y : v[b + m * NB].x;
-                }
-                exchange_sync<ES>();
-#pragma unroll
-                for (int i = 0; i < E; ++i) {
-                    if (part) v[i].y = ds[lds_at<ES>(jt + i * TPL)];
-                    else v[i].x = ds[lds_at<ES>(jt + i * TPL)];
-                }
-                exchange_sync<ES>();
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int j = jt + b * TPL;
-                const int k = j % NS;
-                const int base = (j - k) * R + k;
-#pragma unroll
-                for (int m = 0; m < R; ++m) d[lds_at<ES>(base + m * NS)] = v[b + m * NB];
-            }
-            exchange_sync<ES>();
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = d[lds_at<ES>(jt + i * TPL)];
-            exchange_sync<ES>();
-        }
+        stage_exchange<T, L, E, ES, S, SPLIT>(v, d, jt);
         line_fft<T, L, E, ES, TS, S + 1, TWP, SPLIT>(v, d, jt, tw);
     }
 }

@@ -21,15 +21,19 @@
 namespace tk {
 
 // Stage-combine modes of P5.  h and the factors E = exp(-nu |k|^2 h), E2 = exp(-nu|k|^2 h/2)
-// come from the device step state; N is the projected, masked nonlinear term.
+// come from the device step state; N is the projected, masked nonlinear term.  The
+// accumulator aux carries every term of the new state except the last stage's, so the
+// last stage does not read u:
+//   RK2:  u' = E u + h/2 (E N1 + N2)
+//   RK4:  u' = E u + h/6 (E N1 + 2 E2 N2 + 2 E2 N3 + N4)
 enum NsMode : int {
     NS_RHS = 0,   // out = N
-    RK2_S1 = 1,   // aux = N ;           ust = E (u + h N)
-    RK2_S2 = 2,   // u = E u + h/2 (E aux + N)
-    RK4_S1 = 3,   // aux = E N ;         ust = E2 (u + h/2 N)
-    RK4_S2 = 4,   // aux += 2 E2 N ;     ust = E2 u + h/2 N
-    RK4_S3 = 5,   // aux += 2 E2 N ;     ust = E u + h E2 N
-    RK4_S4 = 6    // u = E u + h/6 (aux + N)
+    RK2_S1 = 1,   // aux = E (u + h/2 N) ;  ust = E (u + h N)
+    RK2_S2 = 2,   // u = aux + h/2 N
+    RK4_S1 = 3,   // aux = E (u + h/6 N) ;  ust = E2 (u + h/2 N)
+    RK4_S2 = 4,   // aux += h/3 E2 N ;      ust = E2 u + h/2 N
+    RK4_S3 = 5,   // aux += h/3 E2 N ;      ust = E u + h E2 N
+    RK4_S4 = 6    // u = aux + h/6 N
 };
 
 // Device step state.
@@ -133,7 +137,12 @@ __device__ __forceinline__ void ns_p1_load(const V2<T> *__restrict__ u, const P1
     }
 }
 
-// u^ and omega^ = i k x u^ (and theta^) transformed along x, stored to w6.
+// u^ and omega^ = i k x u^ (and theta^) transformed along x, stored to w6.  ky and kz are
+// constant along an x line and the transform is linear, so with U = F(u) (F the inverse
+// transform along x) only the kx terms need lines of their own:
+//   omega_x = i ky U_z - i kz U_y,  omega_y = i kz U_x - F(i kx u_z),  omega_z = F(i kx u_y) - i ky U_x,
+// five line transforms for the six outputs.  Steps: 0 U_x (kept), 1 F(i kx u_y), 2 F(i kx
+// u_z), 3 U_y (-i kz U_y kept), 4 U_z, 5 (RBC) theta.
 template <typename T, int L, int E, int W, bool RBC>
 __device__ __forceinline__ void ns_p1_body(const V2<T> (&a0)[E], const V2<T> (&a1)[E], const V2<T> (&a2)[E],
                                            const V2<T> (&a3)[RBC ? E : 1], V2<T> *__restrict__ w6, const P1Col &c,
@@ -142,38 +151,49 @@ __device__ __forceinline__ void ns_p1_body(const V2<T> (&a0)[E], const V2<T> (&a
     constexpr int N = L;
     constexpr int TPL = L / E;
     constexpr int ES = W + 1;
-    constexpr int NOUT = RBC ? 7 : 6;
     constexpr long FSc = (long)N * N * ns_kzp<N>();
     constexpr long RSc = (long)N * ns_kzp<N>();
     const int col = threadIdx.x % W;
     const int jt = threadIdx.x / W;
     const T kyd = ka * (T)c.ky, kzd = ka * (T)((2 * c.kz == N) ? 0 : c.kz);
-#pragma unroll 1
-    for (int f = 0; f < NOUT; ++f) {
-        C v[E];
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const T kx = ka * (T)deriv_k(jt + i * TPL, N);
-            C x;
-            if (f == 0) x = a0[i];
-            else if (f == 1) x = a1[i];
-            else if (f == 2) x = a2[i];
-            else if (RBC && f == 6) x = a3[RBC ? i : 0];
-            else {
-                // omega = i k x u
-                C b;
-                if (f == 3) b = csub(cscale(a2[i], kyd), cscale(a1[i], kzd));
-                else if (f == 4) b = csub(cscale(a0[i], kzd), cscale(a2[i], kx));
-                else b = csub(cscale(a1[i], kx), cscale(a0[i], kyd));
-                x = cmul_pi(b);
-            }
-            v[i] = cconj(x);  // inverse transform as conj(DFT(conj .))
-        }
-        line_fft<T, L, E, ES, 1, 0, true>(v, lds + col, jt, tw);
+    auto store = [&](int f, const C(&y)[E]) {
         if (c.valid) {
 #pragma unroll
-            for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FSc + (long)(i * TPL) * RSc, c.lo2) = cconj(v[i]);
+            for (int i = 0; i < E; ++i) *at_bytes(w6 + f * FSc + (long)(i * TPL) * RSc, c.lo2) = y[i];
         }
+    };
+    // one line transform of the inputs selected by `in`, conjugated back
+    auto xform = [&](C(&v)[E], auto in) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cconj(in(i, ka * (T)deriv_k(jt + i * TPL, N)));
+        line_fft<T, L, E, ES, 1, 0, true>(v, lds + col, jt, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cconj(v[i]);
+    };
+    C ux[E], v[E];
+    xform(ux, [&](int i, T) { return a0[i]; });
+    store(0, ux);
+    xform(v, [&](int i, T kx) { return cmul_pi(cscale(a1[i], kx)); });
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = csub(v[i], cmul_pi(cscale(ux[i], kyd)));
+    store(5, v);
+    xform(v, [&](int i, T kx) { return cmul_pi(cscale(a2[i], kx)); });
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = csub(cmul_pi(cscale(ux[i], kzd)), v[i]);
+    store(4, v);
+    C wx[E];
+    xform(v, [&](int i, T) { return a1[i]; });
+    store(1, v);
+#pragma unroll
+    for (int i = 0; i < E; ++i) wx[i] = cmul_pi(cscale(v[i], -kzd));
+    xform(v, [&](int i, T) { return a2[i]; });
+    store(2, v);
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = cadd(wx[i], cmul_pi(cscale(v[i], kyd)));
+    store(3, v);
+    if constexpr (RBC) {
+        xform(v, [&](int i, T) { return a3[i]; });
+        store(6, v);
     }
 }
 
@@ -243,6 +263,10 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     C nx[E];
     float umx = 0.f;  // lanes of invalid lines hold zeros
     load(nx, 0);
+    // (twiddles held in registers for all nine transforms instead of the LDS table cost
+    // occupancy and measured no faster at 512^3)
+    auto split_tw = [&](int i) { return tw[jt + i * TPL]; };
+    auto xform = [&](C(&v)[E]) { line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw); };
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
         C v[E], xm[E];
@@ -258,10 +282,10 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             C xc = k == 0 ? mk<T>(0, 0) : cconj(xm[i]);
             if (k == 0) xk.y = 0;
             const C a = cadd(xk, xc);
-            const C b = cmul(cconj(tw[k]), csub(xk, xc));
+            const C b = cmul(cconj(split_tw(i)), csub(xk, xc));
             v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
         }
-        line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw);
+        xform(v);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const C w = mk<T>(v[i].x, -v[i].y);
@@ -297,7 +321,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = c[f][i];
-        line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw);
+        xform(v);
         C zm[E];
         mirror<T, L, E>(v, zm, jt);
         if (valid) {
@@ -309,7 +333,7 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
                     const C zk = v[i];
                     const C zc = cconj(zm[i]);
                     const C a = cadd(zk, zc);
-                    const C b = cmul(tw[k], csub(zk, zc));
+                    const C b = cmul(split_tw(i), csub(zk, zc));
                     o[k] = mk<T>((T)0.5 * (a.x + b.y), (T)0.5 * (a.y - b.x));
                 }
             }
@@ -439,30 +463,33 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
             const T th = (T)h;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const C uu = *at(u, f);
                 const C n = nn[f];
                 switch (mode) {
-                case RK2_S1:
-                    *atc(aux, f) = n;
+                case RK2_S1: {
+                    const C uu = *at(u, f);
+                    *atc(aux, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e1);
                     *atc(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
+                }
                 case RK2_S2:
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(cscale(*atc(aux, f), e1), n), (T)0.5 * th));
+                    *at(u, f) = cadd(*atc(aux, f), cscale(n, (T)0.5 * th));
                     break;
-                case RK4_S1:
-                    *atc(aux, f) = cscale(n, e1);
+                case RK4_S1: {
+                    const C uu = *at(u, f);
+                    *atc(aux, f) = cscale(cadd(uu, cscale(n, th / (T)6)), e1);
                     *atc(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
+                }
                 case RK4_S2:
-                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, (T)2 * e2));
-                    *atc(ust, f) = cadd(cscale(uu, e2), cscale(n, (T)0.5 * th));
+                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, th / (T)3 * e2));
+                    *atc(ust, f) = cadd(cscale(*at(u, f), e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
-                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, (T)2 * e2));
-                    *atc(ust, f) = cadd(cscale(uu, e1), cscale(n, th * e2));
+                    *atc(aux, f) = cadd(*atc(aux, f), cscale(n, th / (T)3 * e2));
+                    *atc(ust, f) = cadd(cscale(*at(u, f), e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    *at(u, f) = cadd(cscale(uu, e1), cscale(cadd(*atc(aux, f), n), th / (T)6));
+                    *at(u, f) = cadd(*atc(aux, f), cscale(n, th / (T)6));
                     break;
                 }
             }
@@ -687,8 +714,8 @@ void launch_ns_p1(const void *u, void *w6, int K, int cin, const void *tw, hipSt
     hipLaunchKernelGGL((k_ns_p1<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (const V2<T> *)u,
                        (V2<T> *)w6, K, cin, (const V2<T> *)tw, (T)1);
 }
-template <typename T, int L2, int E2, int LPW> void launch_ns_p3(void *w6, long nlines, int KZC, const void *tw,
-                                                                 float *part, hipStream_t s) {
+template <typename T, int L2, int E2, int LPW>
+void launch_ns_p3(void *w6, long nlines, int KZC, const void *tw, float *part, hipStream_t s) {
     hipLaunchKernelGGL((k_ns_p3<T, L2, E2, LPW>), dim3(cdiv(nlines, LPW)), dim3(LPW * (L2 / E2)), 0, s,
                        (V2<T> *)w6, nlines, KZC, (const V2<T> *)tw, part);
 }
@@ -701,9 +728,9 @@ void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s
 }
 
 // Column-pass variant (E, W) of P1 / P5 (FP32, N >= 128): kept when it differs from the
-// default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  P1 holds
-// three input fields per thread, so it only gets 512-thread variants (a 1024-thread
-// workgroup leaves 128 registers per thread); P5 gets 512 and 1024.  (Persistent P1
+// default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  Both get
+// 512- and 1024-thread tiles of E = default_E(N) (a 1024-thread workgroup leaves 128
+// registers per thread, enough for P1's three input fields at E = 8).  (Persistent P1
 // workgroups loading the next tile ahead measured 1.5x slower at 512^3.)
 template <typename T, int N, int E, int W> constexpr bool ns_x_var_ok() {
     return sizeof(T) == 4 && N >= 128 && E <= N && N % E == 0 && rplan_ok(N, E) && W >= 1 &&
@@ -711,7 +738,7 @@ template <typename T, int N, int E, int W> constexpr bool ns_x_var_ok() {
            !(E == ns_x_E<T>(N) && W == ns_x_W<T>(N));
 }
 template <typename T, int N, int E, int W> void add_ns_p1_var(NsKernels &k) {
-    if constexpr (ns_x_var_ok<T, N, E, W>() && W * (N / E) <= 512) k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
+    if constexpr (ns_x_var_ok<T, N, E, W>()) k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
 }
 template <typename T, int N, int E, int W> void add_ns_p5_var(NsKernels &k) {
     // (a variant loading the stage combine's operands with the input, before the
@@ -747,6 +774,7 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
     k.p3v[k.np3++] = {LPW, E2, 0, &launch_ns_p3<T, L2, E2, LPW>};
     add_ns_p1_var<T, N, Ed, 512 * Ed / N>(k);
+    add_ns_p1_var<T, N, Ed, 1024 * Ed / N>(k);
     add_ns_p5_var<T, N, Ed, 512 * Ed / N>(k);
     add_ns_p5_var<T, N, Ed, 1024 * Ed / N>(k);
     add_ns_z_var<T, N, default_E(L2) / 2>(k);

@@ -337,7 +337,7 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
             if (i > 0) TK_TRY(check(B.w6, B.ref, 6 * nf, &ok));
             float ms;
             TK_TRY(time_it([&] { v.fn(B.w6, (long)n * n, g.KZC, g.ax.twz, nullptr, s); }, iters, s, &ms));
-            snprintf(line, sizeof(line), "pass p3 N=%d LPW=%d E=%d: %.4f ms %s\n", n, v.a, v.E, ms,
+            snprintf(line, sizeof(line), "pass p3 N=%d LPW=%d E=%d v=%d: %.4f ms %s\n", n, v.a, v.E, v.v, ms,
                      ok ? "ok" : "REJECTED");
             rep += line;
             if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
