@@ -147,16 +147,17 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
  * 5, 6 = 0 and 4 with split exchanges (real, then imaginary parts through half the LDS).
  * Passes 3, 4, 5 are the solver passes P1 (a = columns), P3 (a = lines per workgroup) and
  * P5 (a = columns) of an L^3 grid (variant 0), pass 6 the solver's Y passes P2 / P4 (a
- * strided tile as for pass 1); solver handles created afterwards use them.  a <= 0
- * removes the entry.  TK_EUNSUPPORTED if no such tile is compiled. */
+ * strided tile as for pass 1), pass 7 the time stepper's P5 fused with the next P1 (a =
+ * columns); solver handles created afterwards use them.  a <= 0 removes the entry.
+ * TK_EUNSUPPORTED if no such tile is compiled. */
 tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant);
 
-/* Autotune the solver passes P1, P2 / P4, P3 and P5 of an n^3 grid in dtype dt: every
- * compiled tile variant runs on pseudo-random fields of the grid's size, is admitted only
- * if its output matches the first variant's to relative L2 1e-5 (FP32) / 1e-12 (FP64),
- * and is timed (median of iters launches); the fastest admitted variant of each pass goes
- * into the tile table (passes 3, 4, 5, 6).  Allocates 18 spectral fields for the duration
- * of the call.
+/* Autotune the solver passes P1, P2 / P4, P3, P5 and the fused P5 + P1 of an n^3 grid in
+ * dtype dt: every compiled tile variant runs on pseudo-random fields of the grid's size,
+ * is admitted only if its output matches the first variant's (the fused pass: P1's) to
+ * relative L2 1e-5 (FP32) / 1e-12 (FP64), and is timed (median of iters launches); the
+ * fastest admitted variant of each pass goes into the tile table (passes 3..7).
+ * Allocates 18 spectral fields for the duration of the call.
  * report (may be NULL) receives one text line per variant.  Synchronises. */
 tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, int report_len);
 

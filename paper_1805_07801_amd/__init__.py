@@ -158,8 +158,9 @@ def autotune(nx, ny=None, nz=None, batch=1, dtype=None, iters=5):
 
 
 def ns_autotune(n, iters=5, dtype=None):
-    """Time every compiled variant of the solver passes P1, P3, P5 of an n^3 grid and record
-    the fastest one that matches variant 0 (see ns_autotune).  Returns the text report."""
+    """Time every compiled variant of the solver passes P1, P2 / P4, P3, P5 and the fused
+    P5 + P1 of an n^3 grid and record the fastest one that matches the reference (see
+    ns_autotune).  Returns the text report."""
     import torch
     buf = ctypes.create_string_buffer(1 << 14)
     check(lib().ns_autotune(n, _dtype_code(dtype or torch.float32), iters, buf, 1 << 14))
@@ -168,8 +169,9 @@ def ns_autotune(n, iters=5, dtype=None):
 
 def tile_candidates(L, dtype, pass_):
     """[(a, E, v)] compiled tile candidates of (L, dtype, pass): pass 0 = Z (a = threads),
-    1 = Y and 2 = X (a = columns per tile), v = 1 for the persistent strided variant;
-    passes 3, 4, 5 = solver P1, P3, P5 of an L^3 grid."""
+    1 = Y and 2 = X (a = columns per tile), v = the strided kernel variant (see
+    fft3d_tune_set); passes 3, 4, 5 = solver P1, P3, P5 of an L^3 grid, 6 = its Y passes,
+    7 = the fused P5 + P1."""
     code = _dtype_code(dtype)
     n = lib().fft3d_tile_candidates(L, code, pass_, None, None, None, 0)
     a = (ctypes.c_int * max(n, 1))()

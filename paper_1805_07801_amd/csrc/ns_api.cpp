@@ -48,18 +48,23 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt) {
     g->v1 = pick(3, g->nk->p1v, g->nk->np1);
     g->v3 = pick(4, g->nk->p3v, g->nk->np3);
     g->v5 = pick(5, g->nk->p5v, g->nk->np5);
+    g->v51 = pick(7, g->nk->p51v, g->nk->np51);
     const TileChoice cy = tuned_tile(n, dt, 6);
     g->ky = cy.a > 0 ? pick_strided(n, dt, cy.a, cy.E, cy.v) : nullptr;
     if (!g->ky) g->ky = g->ax.ky;
     return TK_OK;
 }
 
+tk_status ns_p1_only(const NsGrid &g, const void *uin, void *w6, hipStream_t s, int uin_transit) {
+    g.nk->p1v[g.v1].fn(uin, w6, g.K, uin_transit, g.ax.twx, s);
+    return launch_check("ns P1");
+}
+
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s, int uin_transit) {
+                      NsState *st_set, hipStream_t s, int uin_transit, int flags) {
     const int n = g.n;
     // P1: x-inverse of u^ and omega^ = i k x u^
-    g.nk->p1v[g.v1].fn(uin, w6, g.K, uin_transit, g.ax.twx, s);
-    TK_TRY(launch_check("ns P1"));
+    if (!(flags & NS_SKIP_P1)) TK_TRY(ns_p1_only(g, uin, w6, s, uin_transit));
     // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
     StridedArgs y2{w6, w6, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
     g.ky->fn(y2, s);
@@ -76,9 +81,14 @@ tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &
     StridedArgs y4{w6, w6, 3L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 0, 1.0, -1, g.K};
     g.ky->fn(y4, s);
     TK_TRY(launch_check("ns P4"));
-    // P5: x-forward, projection, stage combine
+    // P5: x-forward, projection, stage combine (and the next P1)
     P5Args a = p5;
     a.c3 = w6;
+    if (flags & NS_FUSE_P1) {
+        if (p5.mode == NS_RHS || g.nk->np51 == 0) return fail(TK_EINVAL, "no fused P5 for this right-hand side");
+        g.nk->p51v[g.v51].fn(a, g.K, g.KZC, g.ax.twx, s);
+        return launch_check("ns P5+P1");
+    }
     g.nk->p5v[g.v5].fn(a, g.K, g.KZC, g.ax.twx, s);
     return launch_check("ns P5");
 }
@@ -169,6 +179,8 @@ extern "C" tk_status ns_create(tk_ns_t *out, const ns_config *cfg) {
     return TK_OK;
 }
 
+// One step with every P5 fused with the P1 after it: on entry w6 holds P1's output for the
+// state u (ns_p1_only before the first step), on exit P1's output for the new state.
 static tk_status ns_one_step(tk_ns_s *p, void *u, hipStream_t s) {
     const NsGrid &g = p->g;
     P5Args a{};
@@ -177,18 +189,13 @@ static tk_status ns_one_step(tk_ns_s *p, void *u, hipStream_t s) {
     a.ust = p->ust;
     a.st = p->st;
     a.nu = p->cfg.nu;
-    if (p->cfg.scheme == 0) {
-        a.mode = RK2_S1;
-        TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
-        a.mode = RK2_S2;
-        TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s, 1));
-    } else {
-        a.mode = RK4_S1;
-        TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s));
-        for (int m = RK4_S2; m <= RK4_S4; ++m) {
-            a.mode = m;
-            TK_TRY(ns_rhs_eval(g, p->ust, p->w6, a, nullptr, nullptr, s, 1));
-        }
+    const int fl = NS_SKIP_P1 | NS_FUSE_P1;
+    a.mode = p->cfg.scheme == 0 ? RK2_S1 : RK4_S1;
+    TK_TRY(ns_rhs_eval(g, u, p->w6, a, p->umax_part, p->st, s, 0, fl));
+    const int last = p->cfg.scheme == 0 ? RK2_S2 : RK4_S4;
+    for (int m = a.mode + 1; m <= last; ++m) {
+        a.mode = m;
+        TK_TRY(ns_rhs_eval(g, nullptr, p->w6, a, nullptr, nullptr, s, 1, fl));
     }
     return TK_OK;
 }
@@ -249,6 +256,7 @@ extern "C" tk_status ns_step(tk_ns_t p, void *u, double dt, int nsteps, double *
             p->graph = gr;
             p->graph_u = u;
         }
+        TK_TRY(ns_p1_only(p->g, u, p->w6, s));
         for (int i = 0; i < nsteps; ++i) TK_HIP_CHECK(hipGraphLaunch(p->gexec, s));
     }
     NsState hf{};

@@ -24,7 +24,7 @@ struct NsGrid {
     tk_dtype dt;
     FftAxes ax;
     const NsKernels *nk;
-    int v1, v3, v5;  // chosen variants of P1, P3, P5 (autotuner table, else 0)
+    int v1, v3, v5, v51;  // chosen variants of P1, P3, P5, fused P5+P1 (autotuner table, else 0)
     const StridedKernel *ky;  // Y passes P2 / P4 (autotuner table pass 6, else the transform's)
 };
 tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
@@ -33,9 +33,14 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
 // P5 combines according to `mode` (see NsMode); the stage buffers aux and ust are in the
 // transit layout (uin_transit = 1 when uin is ust).  part != null (n^2 floats): P3 records
 // max |u|_1 per workgroup and, when st_set != null, the step-size kernel reduces them
-// after P3.
+// after P3.  flags: NS_SKIP_P1 (w6 already holds P1's output for uin, uin unused),
+// NS_FUSE_P1 (P5 runs fused with the next right-hand side's P1: w6 receives P1's output
+// for the stage input instead of ust; not with NS_RHS).
+enum : int { NS_SKIP_P1 = 1, NS_FUSE_P1 = 2 };
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s, int uin_transit = 0);
+                      NsState *st_set, hipStream_t s, int uin_transit = 0, int flags = 0);
+// P1 alone (the first right-hand side of a run of fused ones).
+tk_status ns_p1_only(const NsGrid &g, const void *uin, void *w6, hipStream_t s, int uin_transit = 0);
 
 // Random solenoidal initial state from real noise [3][n][n][n] (see ns_init_random).
 tk_status ns_init_random_grid(const NsGrid &g, const void *noise, void *u, double energy, double *dscratch,

@@ -378,11 +378,15 @@ struct P5Args {
     int mode;
 };
 
-template <typename T, int L, int E, int W>
-__device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V2<T> *__restrict__ add3, V2<T> *u,
+// FUSE: the stage input (ust, or the new state) the combine forms is kept in registers and
+// transformed on as the next right-hand side's P1 (the same columns, tile by tile) into the
+// six transit fields at w6o, instead of going through the stage buffer: ust is neither
+// written nor read back.  Not for NS_RHS.
+template <typename T, int L, int E, int W, bool FUSE = false>
+__device__ __forceinline__ void ns_p5_tile(const V2<T> *c3, const V2<T> *__restrict__ add3, V2<T> *u,
                                            V2<T> *aux, V2<T> *ust, V2<T> *out, const NsState *__restrict__ st,
                                            double nu, int mode, int K, int KZC, long tile, V2<T> *lds,
-                                           const V2<T> *tw) {
+                                           const V2<T> *tw, V2<T> *w6o = nullptr) {
     using C = V2<T>;
     constexpr int N = L;
     constexpr int NZH = N / 2 + 1;
@@ -431,7 +435,13 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int r = jt + i * TPL;
-            if (!row_kept(r, L, K)) continue;
+            if (!row_kept(r, L, K)) {
+                if constexpr (FUSE) {
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) cf[f][i] = mk<T>(0, 0);
+                }
+                continue;
+            }
             const int kx = wave_k(r, N);
             auto at = [&](auto *b, int f) { return at_bytes(b + f * FS + (long)(i * TPL) * RS, lo); };
             auto atc = [&](auto *b, int f) { return at_bytes(b + f * FSc + (long)(i * TPL) * RSc, loc); };
@@ -464,36 +474,48 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *__restrict__ c3, const V
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 const C n = nn[f];
+                C next;  // the next right-hand side's input
                 switch (mode) {
                 case RK2_S1: {
                     const C uu = *at(u, f);
                     *atc(aux, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e1);
-                    *atc(ust, f) = cscale(cadd(uu, cscale(n, th)), e1);
+                    next = cscale(cadd(uu, cscale(n, th)), e1);
                     break;
                 }
                 case RK2_S2:
-                    *at(u, f) = cadd(*atc(aux, f), cscale(n, (T)0.5 * th));
+                    next = cadd(*atc(aux, f), cscale(n, (T)0.5 * th));
+                    *at(u, f) = next;
                     break;
                 case RK4_S1: {
                     const C uu = *at(u, f);
                     *atc(aux, f) = cscale(cadd(uu, cscale(n, th / (T)6)), e1);
-                    *atc(ust, f) = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
+                    next = cscale(cadd(uu, cscale(n, (T)0.5 * th)), e2);
                     break;
                 }
                 case RK4_S2:
                     *atc(aux, f) = cadd(*atc(aux, f), cscale(n, th / (T)3 * e2));
-                    *atc(ust, f) = cadd(cscale(*at(u, f), e2), cscale(n, (T)0.5 * th));
+                    next = cadd(cscale(*at(u, f), e2), cscale(n, (T)0.5 * th));
                     break;
                 case RK4_S3:
                     *atc(aux, f) = cadd(*atc(aux, f), cscale(n, th / (T)3 * e2));
-                    *atc(ust, f) = cadd(cscale(*at(u, f), e1), cscale(n, th * e2));
+                    next = cadd(cscale(*at(u, f), e1), cscale(n, th * e2));
                     break;
                 default:  // RK4_S4
-                    *at(u, f) = cadd(*atc(aux, f), cscale(n, th / (T)6));
+                    next = cadd(*atc(aux, f), cscale(n, th / (T)6));
+                    *at(u, f) = next;
                     break;
                 }
+                if constexpr (FUSE) cf[f][i] = next;
+                else if (mode != RK2_S2 && mode != RK4_S4) *atc(ust, f) = next;
             }
         }
+    }
+    if constexpr (FUSE) {
+        // the LDS is free again: the last exchange of the forward transforms ended with a
+        // barrier after every thread's reads
+        const P1Col c = ns_p1_col<T, L, E, W>(tile, K, 1);
+        const C none[1] = {mk<T>(0, 0)};
+        ns_p1_body<T, L, E, W, false>(cf[0], cf[1], cf[2], none, w6o, c, lds, tw, (T)1);
     }
 }
 
@@ -509,6 +531,22 @@ __global__ __launch_bounds__(W *(L / E)) void k_ns_p5(const V2<T> *__restrict__ 
     __syncthreads();
     ns_p5_tile<T, L, E, W>(c3, add3, u, aux, ust, out, st, nu, mode, K, KZC, xcd_tile(blockIdx.x, gridDim.x), lds,
                            tw);
+}
+
+// P5 fused with the next right-hand side's P1: reads the products from w6 (fields 0..2)
+// and writes the next six transit fields over them (each workgroup reads its columns
+// whole before it writes them).
+template <typename T, int L, int E, int W>
+__global__ __launch_bounds__(W *(L / E)) void k_ns_p51(V2<T> *w6, const V2<T> *__restrict__ add3, V2<T> *u,
+                                                        V2<T> *aux, const NsState *__restrict__ st, double nu,
+                                                        int mode, int K, int KZC, const V2<T> *__restrict__ twg) {
+    using C = V2<T>;
+    __shared__ C lds[L * (W + 1)];
+    __shared__ C tw[L];
+    load_twiddles<T>(tw, twg, L, threadIdx.x, W * (L / E));
+    __syncthreads();
+    ns_p5_tile<T, L, E, W, true>(w6, add3, u, aux, nullptr, nullptr, st, nu, mode, K, KZC,
+                                 xcd_tile(blockIdx.x, gridDim.x), lds, tw, w6);
 }
 
 // ---- P5 of the Boussinesq (RBC) right-hand side ----------------------------------------------------
@@ -695,10 +733,11 @@ constexpr int NS_MAXVAR = 6;
 struct NsKernels {
     int N;
     tk_dtype dt;
-    int np1 = 0, np3 = 0, np5 = 0;
+    int np1 = 0, np3 = 0, np5 = 0, np51 = 0;
     NsVar<NsP1Fn> p1v[NS_MAXVAR];
     NsVar<NsP3Fn> p3v[NS_MAXVAR];
     NsVar<NsP5Fn> p5v[NS_MAXVAR];
+    NsVar<NsP5Fn> p51v[NS_MAXVAR];  // P5 fused with the next P1 (a.c3 = the workspace, rewritten)
     // Boussinesq variants (default shapes): P1 with temperature (4 -> 7 fields), P3 (7 -> 6),
     // P5 (6 + state of 4)
     void (*p1r)(const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s);
@@ -726,6 +765,13 @@ void launch_ns_p5(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s
                        (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, (V2<T> *)a.ust, (V2<T> *)a.out, a.st,
                        a.nu, a.mode, K, KZC, (const V2<T> *)tw);
 }
+template <typename T, int N, int E, int W>
+void launch_ns_p51(const P5Args &a, int K, int KZC, const void *tw, hipStream_t s) {
+    const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
+    hipLaunchKernelGGL((k_ns_p51<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s, (V2<T> *)a.c3,
+                       (const V2<T> *)a.add3, (V2<T> *)a.u, (V2<T> *)a.aux, a.st, a.nu, a.mode, K, KZC,
+                       (const V2<T> *)tw);
+}
 
 // Column-pass variant (E, W) of P1 / P5 (FP32, N >= 128): kept when it differs from the
 // default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  Both get
@@ -743,7 +789,10 @@ template <typename T, int N, int E, int W> void add_ns_p1_var(NsKernels &k) {
 template <typename T, int N, int E, int W> void add_ns_p5_var(NsKernels &k) {
     // (a variant loading the stage combine's operands with the input, before the
     // transforms, measured 10% slower at 512^3: the registers it takes cost occupancy)
-    if constexpr (ns_x_var_ok<T, N, E, W>()) k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
+    if constexpr (ns_x_var_ok<T, N, E, W>()) {
+        k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
+        k.p51v[k.np51++] = {W, E, 0, &launch_ns_p51<T, N, E, W>};
+    }
 }
 // Line-pass variant E2 of P3 (FP32, N >= 128; L2 = N / 2 points per complex line, 256
 // threads): kept when it differs from the default and a line stays inside one wavefront.
@@ -772,6 +821,7 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     k.dt = sizeof(T) == 4 ? TK_F32 : TK_F64;
     k.p1v[k.np1++] = {W, E, 0, &launch_ns_p1<T, N, E, W>};
     k.p5v[k.np5++] = {W, E, 0, &launch_ns_p5<T, N, E, W>};
+    k.p51v[k.np51++] = {W, E, 0, &launch_ns_p51<T, N, E, W>};
     k.p3v[k.np3++] = {LPW, E2, 0, &launch_ns_p3<T, L2, E2, LPW>};
     add_ns_p1_var<T, N, Ed, 512 * Ed / N>(k);
     add_ns_p1_var<T, N, Ed, 1024 * Ed / N>(k);

@@ -186,18 +186,19 @@ template <typename V> static int ns_var_index(const V *v, int nv, int a, int E, 
 }
 
 extern "C" tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant) {
-    if (pass < 0 || pass > 6) return fail(TK_EINVAL, "pass must be 0..6");
+    if (pass < 0 || pass > 7) return fail(TK_EINVAL, "pass must be 0..7");
     if (a <= 0) {
         set_tuned_tile(L, dt, pass, {0, 0, 0});
         return TK_OK;
     }
     bool found = false;
-    if (pass >= 3 && pass <= 5) {
+    if ((pass >= 3 && pass <= 5) || pass == 7) {
         const NsKernels *k = ns_kernels_of(L, dt);
         if (k) {
             if (pass == 3) found = ns_var_index(k->p1v, k->np1, a, E, variant) >= 0;
             else if (pass == 4) found = ns_var_index(k->p3v, k->np3, a, E, variant) >= 0;
-            else found = ns_var_index(k->p5v, k->np5, a, E, variant) >= 0;
+            else if (pass == 5) found = ns_var_index(k->p5v, k->np5, a, E, variant) >= 0;
+            else found = ns_var_index(k->p51v, k->np51, a, E, variant) >= 0;
         }
     } else if (pass == 0) {
         for (const auto &k : z_kernels()) found |= (k.N == L && k.dt == dt && k.nt == a && k.E == E && variant == 0);
@@ -217,21 +218,21 @@ extern "C" tk_status fft3d_tune_clear(void) {
 
 extern "C" int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int *v, int cap) {
     int n = 0;
-    if (pass >= 3 && pass <= 5) {
+    if ((pass >= 3 && pass <= 5) || pass == 7) {
         const NsKernels *k = ns_kernels_of(L, dt);
         if (!k) return 0;
-        const int nv = pass == 3 ? k->np1 : pass == 4 ? k->np3 : k->np5;
-        for (int i = 0; i < nv; ++i) {
-            if (i < cap) {
-                const int ai = pass == 3 ? k->p1v[i].a : pass == 4 ? k->p3v[i].a : k->p5v[i].a;
-                const int Ei = pass == 3 ? k->p1v[i].E : pass == 4 ? k->p3v[i].E : k->p5v[i].E;
-                const int vi = pass == 3 ? k->p1v[i].v : pass == 4 ? k->p3v[i].v : k->p5v[i].v;
-                if (a) a[i] = ai;
-                if (E) E[i] = Ei;
-                if (v) v[i] = vi;
+        auto list = [&](const auto *vs, int nv) {
+            for (int i = 0; i < nv && i < cap; ++i) {
+                if (a) a[i] = vs[i].a;
+                if (E) E[i] = vs[i].E;
+                if (v) v[i] = vs[i].v;
             }
-        }
-        return nv;
+            return nv;
+        };
+        if (pass == 3) return list(k->p1v, k->np1);
+        if (pass == 4) return list(k->p3v, k->np3);
+        if (pass == 5) return list(k->p5v, k->np5);
+        return list(k->p51v, k->np51);
     }
     if (pass == 0) {
         for (const auto &k : z_kernels())
@@ -260,7 +261,8 @@ extern "C" int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *
 // ---- solver passes ---------------------------------------------------------------------------------
 // Each variant of P1, P3 and P5 of an n^3 grid runs on the same pseudo-random fields; it is
 // admitted when its output matches variant 0's to the transform tolerance, timed like the
-// FFT candidates, and the fastest admitted one goes into the tile table (passes 3, 4, 5).
+// FFT candidates, and the fastest admitted one goes into the tile table (passes 3, 4, 5;
+// the solver's Y passes 6, the fused P5 + P1 7).
 struct NsTuneBufs {
     void *u = nullptr, *w6 = nullptr, *in6 = nullptr, *ref = nullptr, *out = nullptr;
     NsState *st = nullptr;
@@ -400,6 +402,46 @@ extern "C" tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, in
             if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
         }
         finish(5, ba, bE, bv, best);
+    }
+    // P5 fused with P1: with the zeroed step state (h = 0) the first RK2 stage hands u on
+    // unchanged, so the fused pass must reproduce P1 of u over the products in w6; timed as
+    // the second RK2 stage (reads aux, writes u and w6)
+    if (k->np51 > 0) {
+        float best = 1e30f;
+        int ba = 0, bE = 0, bv = 0;
+        const size_t h3 = 3 * fb;
+        auto setup = [&]() -> tk_status {
+            TK_HIP_CHECK(hipMemcpyAsync(B.w6, B.in6, h3, hipMemcpyDeviceToDevice, s));
+            TK_HIP_CHECK(hipMemsetAsync((char *)B.w6 + h3, 0, h3, s));
+            return TK_OK;
+        };
+        TK_TRY(setup());
+        k->p1v[0].fn(B.u, B.w6, g.K, 0, g.ax.twx, s);
+        TK_TRY(launch_check("autotune P5+P1 reference"));
+        TK_HIP_CHECK(hipMemcpyAsync(B.ref, B.w6, 6 * fb, hipMemcpyDeviceToDevice, s));
+        P5Args a{};
+        a.c3 = B.w6;
+        a.u = B.u;
+        a.aux = B.out;
+        a.st = B.st;
+        a.mode = RK2_S1;
+        P5Args a2 = a;
+        a2.mode = RK2_S2;
+        for (int i = 0; i < k->np51; ++i) {
+            const auto &v = k->p51v[i];
+            TK_TRY(setup());
+            v.fn(a, g.K, g.KZC, g.ax.twx, s);
+            TK_TRY(launch_check("autotune P5+P1"));
+            bool ok = true;
+            TK_TRY(check(B.w6, B.ref, 12 * nf, &ok));
+            float ms;
+            TK_TRY(time_it([&] { v.fn(a2, g.K, g.KZC, g.ax.twx, s); }, iters, s, &ms));
+            snprintf(line, sizeof(line), "pass p51 N=%d W=%d E=%d v=%d: %.4f ms %s\n", n, v.a, v.E, v.v, ms,
+                     ok ? "ok" : "REJECTED");
+            rep += line;
+            if (ok && ms < best) best = ms, ba = v.a, bE = v.E, bv = v.v;
+        }
+        finish(7, ba, bE, bv, best);
     }
     TK_HIP_CHECK(hipStreamSynchronize(s));
     if (report && report_len > 0) {

@@ -4,7 +4,7 @@
 
 Every candidate is checked against the default tile before it may be chosen (see
 fft3d_autotune and ns_autotune in include/tk.h); the file records the choice per
-(length, dtype, pass), passes 3-5 being the solver's P1, P3 and P5.
+(length, dtype, pass), passes 3-7 being the solver's P1, P3, P5, Y passes and fused P5 + P1.
 """
 import argparse
 import os

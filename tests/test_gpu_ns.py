@@ -96,6 +96,43 @@ def test_one_step_vs_oracle(tk, n, dt, scheme):
     assert err <= (1e-12 if dt == "f64" else 1e-4), err
 
 
+@pytest.mark.parametrize("scheme", ["rk2", "rk4"])
+def test_fused_stepper_every_variant_and_state_change(tk, scheme):
+    """Inside a run of steps every P5 runs fused with the next right-hand side's P1 (the
+    stage input never goes through memory).  Every compiled fused variant must reproduce
+    the oracle over several steps, and a state changed between two calls must be picked
+    up (each call transforms its state afresh before the first step)."""
+    import torch
+    n = 128
+    u = rand_state(n, seed=7)
+    nu, h = 2e-3, 0.004
+    stepper = ons.ifrk2_step if scheme == "rk2" else ons.ifrk4_step
+
+    def ref_steps(v, k):
+        for _ in range(k):
+            r = stepper(v, nu, h)
+            v = r[0] if isinstance(r, tuple) else r
+        return v
+
+    ref = ref_steps(u, 2)
+    ref2 = ref_steps(0.5 * ref, 1)
+    cands = tk.tile_candidates(n, torch.float32, 7)
+    assert cands
+    try:
+        for (a, E, v) in cands:
+            tk.tune_set(n, torch.float32, 7, a, E, v)
+            s = tk.NS(n, dtype=torch.float32, nu=nu, scheme=scheme)
+            ud = to_gpu(u, "f32")
+            s.step(ud, h, 2)
+            assert diag.rel_l2(ud.cpu().numpy(), ref, n) <= 1e-4, (a, E, v)
+            ud.mul_(0.5)
+            s.step(ud, h, 1)
+            assert diag.rel_l2(ud.cpu().numpy(), ref2, n) <= 1e-4, (a, E, v)
+            s.close()
+    finally:
+        tk.tune_clear()
+
+
 def test_cfl_step_vs_oracle(tk):
     n = 64
     u = rand_state(n, seed=1)
