@@ -138,8 +138,13 @@ def kernel_names(desc, n):
     for p, keys in ((1, ("y_fwd", "y_inv")), (2, ("x_fwd", "x_inv"))):
         m = re.search(r"W=(\d+) E=(\d+) v=(\d+)", desc[p])
         if m:
-            kern = "k_strided_pp" if m.group(3) in ("1", "2", "3") else "k_strided"
-            names[keys[0]] = names[keys[1]] = "%s<float, %d, %s, %s, false>" % (kern, n, m.group(2), m.group(1))
+            v = m.group(3)
+            if v in ("1", "2", "3"):  # persistent: <T, L, E, W, MASK>
+                name = "k_strided_pp<float, %d, %s, %s, false>" % (n, m.group(2), m.group(1))
+            else:  # one tile per workgroup: <T, L, E, W, MASK, SPLIT>
+                name = "k_strided<float, %d, %s, %s, false, %s>" % (n, m.group(2), m.group(1),
+                                                                     "true" if v in ("5", "6") else "false")
+            names[keys[0]] = names[keys[1]] = name
     return names
 
 
