@@ -121,6 +121,24 @@ __global__ __launch_bounds__(BNT) void kb_p5(const BInst *__restrict__ inst, con
     }
 }
 
+// P5 of the first stage fused with the second stage's P1 (the stage input stays in
+// registers; see ns_p5_tile).
+template <int N>
+__global__ __launch_bounds__(BNT) void kb_p51(const BInst *__restrict__ inst, const BItem *__restrict__ items,
+                                              int nitems, int mode) {
+    __shared__ float2 smem[BCfg<N>::lds_x];
+    float2 *tw = smem;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem w = items[it];
+        const BInst &d = inst[w.inst];
+        __syncthreads();
+        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
+        __syncthreads();
+        ns_p5_tile<float, N, BCfg<N>::E, BCfg<N>::W, true>(d.w6, nullptr, d.u, d.aux, nullptr, nullptr, d.st, d.nu,
+                                                           mode, d.K, d.KZC, w.tile, smem + N, tw, d.w6);
+    }
+}
+
 // Step size of the members of grid size n (the other members belong to other size classes).
 __global__ void kb_set_h(const BInst *__restrict__ inst, int count, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,13 +162,14 @@ struct BClassFns {
     void (*y)(const BInst *, const BItem *, int, int, int);
     void (*p3)(const BInst *, const BItem *, int, int);
     void (*p5)(const BInst *, const BItem *, int, int);
+    void (*p51)(const BInst *, const BItem *, int, int);
 };
 static BClassFns class_fns(int n) {
 #define TK_FNS(N) \
-    if (n == N) return {N, &kb_p1<N>, &kb_y<N>, &kb_p3<N>, &kb_p5<N>};
+    if (n == N) return {N, &kb_p1<N>, &kb_y<N>, &kb_p3<N>, &kb_p5<N>, &kb_p51<N>};
     TK_BATCH_SIZES(TK_FNS)
 #undef TK_FNS
-    return {0, nullptr, nullptr, nullptr, nullptr};
+    return {0, nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 // Tiles per instance of each pass.
@@ -217,8 +236,9 @@ static void nsb_free(tk_nsb_s *b) {
 }
 
 // One IF-RK2 step of every member as one graph: each size class runs its own chain of
-// passes (P1, Y, P3, step size, Y, P5, twice) on a stream of its own, forked from and
-// joined to the capture stream, so the classes' kernels overlap on the GPU.
+// passes (P1, Y, P3, step size, Y, P5 fused with the second stage's P1, then Y, P3, Y,
+// P5) on a stream of its own, forked from and joined to the capture stream, so the
+// classes' kernels overlap on the GPU.
 static tk_status nsb_capture(tk_nsb_s *b) {
     const int nc = (int)b->cls_n.size();
     hipStream_t cs;
@@ -252,14 +272,16 @@ static tk_status nsb_capture(tk_nsb_s *b) {
         const auto &ni = b->nitems[c];
         auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, ni[list])); };
         for (int stage = 0; stage < 2; ++stage) {
-            hipLaunchKernelGGL(f.p1, dim3(g(4)), dim3(BNT), 0, q, b->dinst, it[4], ni[4], stage);
+            if (stage == 0) hipLaunchKernelGGL(f.p1, dim3(g(4)), dim3(BNT), 0, q, b->dinst, it[4], ni[4], 0);
             hipLaunchKernelGGL(f.y, dim3(g(1)), dim3(BNT), 0, q, b->dinst, it[1], ni[1], 6, 1);
             hipLaunchKernelGGL(f.p3, dim3(g(2)), dim3(BNT), 0, q, b->dinst, it[2], ni[2], stage == 0);
             if (stage == 0)
                 hipLaunchKernelGGL(kb_set_h, dim3(cdiv(b->count, 64)), dim3(64), 0, q, b->dinst, b->count, f.n);
             hipLaunchKernelGGL(f.y, dim3(g(3)), dim3(BNT), 0, q, b->dinst, it[3], ni[3], 3, 0);
-            hipLaunchKernelGGL(f.p5, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0],
-                               stage == 0 ? (int)RK2_S1 : (int)RK2_S2);
+            if (stage == 0)
+                hipLaunchKernelGGL(f.p51, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0], (int)RK2_S1);
+            else
+                hipLaunchKernelGGL(f.p5, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0], (int)RK2_S2);
         }
         e = hipEventRecord(ev[c], q);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[c], 0);
