@@ -245,8 +245,26 @@ def cpu_baseline(n=512):
     }
 
 
+def ns_pass_bytes(n):
+    """Algorithmic HBM bytes (read, write) of each solver pass at n^3 FP32: kept modes of
+    the 2/3 rule (K = (n-1)//3), transit rows of KZP complex values."""
+    K = (n - 1) // 3
+    KZP = min((K + 1 + 15) // 16 * 16, n // 2 + 1)
+    kk = 2 * K + 1
+    c = 8
+    return {
+        "P1": (3 * kk * kk * KZP * c, 6 * n * kk * KZP * c),
+        "P2": (6 * n * KZP * kk * c, 6 * n * KZP * n * c),
+        "P3": (6 * n * n * (K + 1) * c, 3 * n * n * KZP * c),
+        "P4": (3 * n * KZP * n * c, 3 * n * KZP * kk * c),
+        "P5": (3 * n * kk * KZP * c, 3 * kk * kk * KZP * c),
+        "P5+P1": (3 * n * kk * KZP * c + 3 * kk * kk * KZP * c, 3 * kk * kk * KZP * c + 6 * n * kk * KZP * c),
+    }
+
+
 def ns_steps_per_s(tk, torch, n, steps, warmup):
-    """RK2 steps/s of the 512^3 decaying-turbulence configuration (CFL 0.5, nu 1e-3)."""
+    """RK2 steps/s of the 512^3 decaying-turbulence configuration (CFL 0.5, nu 1e-3), and
+    the achieved HBM rate of each solver pass (HIP events around each pass)."""
     import synth
     ns = tk.NS(n, dtype=torch.float32, nu=1e-3, cfl=0.5)
     noise = torch.from_numpy(synth.gaussian_field((3, n, n, n), 1)).cuda()
@@ -259,8 +277,16 @@ def ns_steps_per_s(tk, torch, n, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     e = ns.diagnostics(u)["energy"]
+    pt = ns.pass_times(u, iters=5)
     ns.close()
-    return steps / dt, e
+    passes = {}
+    for k, (r, w) in ns_pass_bytes(n).items():
+        ms = pt.get(k, 0.0)
+        if ms > 0:
+            gbps = (r + w) / (ms * 1e-3) / 1e9
+            passes[k] = {"ms": round(ms, 4), "alg_MB": round((r + w) / 1e6, 1), "GBps": round(gbps, 1),
+                         "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 3)}
+    return steps / dt, e, passes
 
 
 def tg32_steps_per_s(tk, torch, steps=200):
@@ -358,9 +384,10 @@ def main():
             "roundtrip_rel_l2": err2,
         }
     if not args.no_ns and hasattr(tk, "NS"):
-        sps, e = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 2), 2)
+        sps, e, nsp = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 2), 2)
         out["ns512_rk2_steps_per_s"] = round(sps, 2)
         out["ns512_energy_after"] = e
+        out["ns512_passes"] = nsp
         out["tg32_fp64_rk2_steps_per_s"] = round(tg32_steps_per_s(tk, torch), 1)
     if not args.no_extra:
         out.update(ensemble_rate(tk, torch))

@@ -215,6 +215,15 @@ tk_status ns_init_random(tk_ns_t ns, const void *noise, void *uhat_out, double e
 /* Last step size used by ns_step (host value; synchronises nothing). */
 tk_status ns_last_dt(tk_ns_t ns, double *dt);
 
+/* Mean duration in ms of each pass of the right-hand side of state uhat, over iters runs
+ * timed with HIP events on `stream` (passes of Section "Spectral Solver": curl and
+ * X-inverse P1, Y-inverse P2, the fused Z pass with u x omega P3, Y-forward P4, X-forward
+ * with projection P5), then of the time stepper's P5 fused with the next P1 (timed in
+ * its first-stage form, which writes only the solver's workspace).  ms[0..5] = P1, P2,
+ * P3, P4, P5, P5+P1.  uhat is read, never written; the workspace and the step state's
+ * CFL maximum are overwritten (ns_step starts afresh).  Synchronises. */
+tk_status ns_pass_times(tk_ns_t ns, const void *uhat, int iters, float ms[6], void *stream);
+
 tk_status ns_destroy(tk_ns_t ns);
 
 /* Energy transfer (the paper lists energy flux and shell-to-shell transfer among the

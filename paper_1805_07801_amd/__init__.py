@@ -69,6 +69,7 @@ def _declare(L):
         "ns_diagnostics": ([vp, vp, P(d), P(d), P(d), i, P(d), vp], i),
         "ns_init_random": ([vp, vp, vp, d, vp], i),
         "ns_last_dt": ([vp, P(d)], i),
+        "ns_pass_times": ([vp, vp, i, P(ctypes.c_float), vp], i),
         "ns_destroy": ([vp], i),
         "ns_energy_transfer": ([vp, vp, P(d), i, vp], i),
         "rbc_create": ([P(vp), P(RbcConfig)], i),
@@ -342,6 +343,14 @@ class NS:
         d = ctypes.c_double()
         check(lib().ns_last_dt(self.h, ctypes.byref(d)))
         return d.value
+
+    def pass_times(self, u, iters=5, stream=None):
+        """Mean ms per pass of one right-hand side of u: P1, P2, P3, P4, P5 and the time
+        stepper's fused P5+P1 (see ns_pass_times)."""
+        self._check_state(u)
+        t = (ctypes.c_float * 6)()
+        check(lib().ns_pass_times(self.h, _ptr(u), int(iters), t, _stream(stream)))
+        return dict(zip(["P1", "P2", "P3", "P4", "P5", "P5+P1"], [t[i] for i in range(6)]))
 
     def diagnostics(self, u, nshell=None, stream=None):
         self._check_state(u)

@@ -61,14 +61,21 @@ tk_status ns_p1_only(const NsGrid &g, const void *uin, void *w6, hipStream_t s, 
 }
 
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s, int uin_transit, int flags) {
+                      NsState *st_set, hipStream_t s, int uin_transit, int flags, hipEvent_t *ev) {
     const int n = g.n;
+    auto mark = [&](int i) -> tk_status {
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[i], s));
+        return TK_OK;
+    };
+    TK_TRY(mark(0));
     // P1: x-inverse of u^ and omega^ = i k x u^
     if (!(flags & NS_SKIP_P1)) TK_TRY(ns_p1_only(g, uin, w6, s, uin_transit));
+    TK_TRY(mark(1));
     // P2: y-inverse of the 6 fields, kept kz columns, kept ky rows read
     StridedArgs y2{w6, w6, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
     g.ky->fn(y2, s);
     TK_TRY(launch_check("ns P2"));
+    TK_TRY(mark(2));
     // P3: z fused c2r -> u x omega -> r2c
     g.nk->p3v[g.v3].fn(w6, (long)n * n, g.KZC, g.ax.twz, part, s);
     TK_TRY(launch_check("ns P3"));
@@ -77,20 +84,24 @@ tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &
         hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(1024), 0, s, st_set, part, nparts);
         TK_TRY(launch_check("ns step size"));
     }
+    TK_TRY(mark(3));
     // P4: y-forward of the 3 products, kept ky rows written
     StridedArgs y4{w6, w6, 3L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 0, 1.0, -1, g.K};
     g.ky->fn(y4, s);
     TK_TRY(launch_check("ns P4"));
+    TK_TRY(mark(4));
     // P5: x-forward, projection, stage combine (and the next P1)
     P5Args a = p5;
     a.c3 = w6;
     if (flags & NS_FUSE_P1) {
         if (p5.mode == NS_RHS || g.nk->np51 == 0) return fail(TK_EINVAL, "no fused P5 for this right-hand side");
         g.nk->p51v[g.v51].fn(a, g.K, g.KZC, g.ax.twx, s);
-        return launch_check("ns P5+P1");
+        TK_TRY(launch_check("ns P5+P1"));
+    } else {
+        g.nk->p5v[g.v5].fn(a, g.K, g.KZC, g.ax.twx, s);
+        TK_TRY(launch_check("ns P5"));
     }
-    g.nk->p5v[g.v5].fn(a, g.K, g.KZC, g.ax.twx, s);
-    return launch_check("ns P5");
+    return mark(5);
 }
 
 // Random solenoidal initial state: r2c of the noise, projection, 2/3 mask and k = 0
@@ -264,6 +275,60 @@ extern "C" tk_status ns_step(tk_ns_t p, void *u, double dt, int nsteps, double *
     TK_HIP_CHECK(hipStreamSynchronize(s));
     if (t_inout) *t_inout = hf.t;
     p->last_dt = hf.h;
+    return TK_OK;
+}
+
+extern "C" tk_status ns_pass_times(tk_ns_t p, const void *uhat, int iters, float ms[6], void *stream) {
+    if (!p || !uhat || !ms) return fail(TK_EINVAL, "NULL argument");
+    if (iters < 1) return fail(TK_EINVAL, "iters must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const NsGrid &g = p->g;
+    hipEvent_t ev[8] = {};
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) hipEventDestroy(f);
+            return fail(TK_EHIP, "event creation failed");
+        }
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    tk_status st = TK_OK;
+    for (int it = 0; it < iters && st == TK_OK; ++it) {
+        // one right-hand side (P5 writes its result into the stage-input buffer)
+        P5Args a{};
+        a.u = const_cast<void *>(uhat);
+        a.out = p->ust;
+        a.st = p->st;
+        a.nu = p->cfg.nu;
+        a.mode = NS_RHS;
+        st = ns_rhs_eval(g, uhat, p->w6, a, nullptr, nullptr, s, 0, 0, ev);
+        // the fused pass in its first-stage form: reads the workspace and u, writes aux
+        // and the workspace
+        if (st == TK_OK && g.nk->np51 > 0) {
+            P5Args b = a;
+            b.c3 = p->w6;
+            b.aux = p->aux;
+            b.mode = RK2_S1;
+            if (hipEventRecord(ev[6], s) != hipSuccess) st = fail(TK_EHIP, "event record failed");
+            g.nk->p51v[g.v51].fn(b, g.K, g.KZC, g.ax.twx, s);
+            if (st == TK_OK) st = launch_check("ns P5+P1");
+            if (st == TK_OK && hipEventRecord(ev[7], s) != hipSuccess) st = fail(TK_EHIP, "event record failed");
+        }
+        if (st == TK_OK && hipEventSynchronize(ev[g.nk->np51 > 0 ? 7 : 5]) != hipSuccess)
+            st = fail(TK_EHIP, "event synchronisation failed");
+        for (int i = 0; i < 5 && st == TK_OK; ++i) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = fail(TK_EHIP, "event timing failed");
+            acc[i] += t;
+        }
+        if (st == TK_OK && g.nk->np51 > 0) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[6], ev[7]) != hipSuccess) st = fail(TK_EHIP, "event timing failed");
+            acc[5] += t;
+        }
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    TK_TRY(st);
+    for (int i = 0; i < 6; ++i) ms[i] = (float)(acc[i] / iters);
     return TK_OK;
 }
 

@@ -37,8 +37,10 @@ tk_status ns_grid_init(NsGrid *g, int n, tk_dtype dt);
 // NS_FUSE_P1 (P5 runs fused with the next right-hand side's P1: w6 receives P1's output
 // for the stage input instead of ust; not with NS_RHS).
 enum : int { NS_SKIP_P1 = 1, NS_FUSE_P1 = 2 };
+// ev (optional, 6 events): recorded before P1 and after each of P1..P5.
 tk_status ns_rhs_eval(const NsGrid &g, const void *uin, void *w6, const P5Args &p5, float *part,
-                      NsState *st_set, hipStream_t s, int uin_transit = 0, int flags = 0);
+                      NsState *st_set, hipStream_t s, int uin_transit = 0, int flags = 0,
+                      hipEvent_t *ev = nullptr);
 // P1 alone (the first right-hand side of a run of fused ones).
 tk_status ns_p1_only(const NsGrid &g, const void *uin, void *w6, hipStream_t s, int uin_transit = 0);
 

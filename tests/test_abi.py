@@ -54,3 +54,12 @@ def test_plan_rejects_bad_arguments(lib):
     assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 1, 7, 0) == tk.TK_EUNSUPPORTED
     assert lib.fft3d_r2c(None, None, None, None) == tk.TK_EINVAL
     assert lib.fft3d_plan_destroy(None) == tk.TK_OK
+
+
+def test_solver_entry_points_reject_null_handles(lib):
+    import paper_1805_07801_amd as tk
+    t = (ctypes.c_float * 6)()
+    assert lib.ns_pass_times(None, None, 1, t, None) == tk.TK_EINVAL
+    assert lib.ns_step(None, None, 0.1, 1, None, None) == tk.TK_EINVAL
+    assert lib.ns_rhs(None, None, None, None) == tk.TK_EINVAL
+    assert lib.ns_destroy(None) == tk.TK_OK

@@ -210,3 +210,22 @@ def test_rhs_512_vs_oracle(tk):
     got = s.rhs(ud).cpu().numpy()
     ref = ons.rhs(u)
     assert diag.rel_l2(got, ref, n) <= 1e-5
+
+
+def test_pass_times_leave_the_state_alone(tk):
+    """ns_pass_times times every solver pass (and the fused one) without writing the
+    state; a step afterwards still matches the oracle (it transforms the state afresh)."""
+    import torch
+    n = 64
+    u = rand_state(n, seed=21)
+    s = tk.NS(n, dtype=torch.float32, nu=2e-3)
+    ud = to_gpu(u, "f32")
+    before = ud.clone()
+    t = s.pass_times(ud, iters=3)
+    assert set(t) == {"P1", "P2", "P3", "P4", "P5", "P5+P1"}
+    assert all(v > 0 for v in t.values()), t
+    assert torch.equal(ud, before)
+    s.step(ud, 0.004, 1)
+    ref = ons.ifrk2_step(u, 2e-3, 0.004)[0]
+    assert diag.rel_l2(ud.cpu().numpy(), ref, n) <= 1e-4
+    s.close()
