@@ -25,59 +25,135 @@ __device__ __forceinline__ uint16_t f32_bf16(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz and Stegun, Handbook of Mathematical
+// Functions, eq. 7.1.26 (absolute error <= 1.5e-7 on x >= 0, odd extension):
+//   erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x).
+// Branch-free (one reciprocal, one exponential), where the library erf takes two
+// divergent ranges: the network's activations are its main vector-ALU cost.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * ax * ax);  // exp(-x^2)
+    return copysignf(fmaf(-q * t, e, 1.0f), x);
+}
+// GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2 and its derivative Phi(x) + x phi(x).
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+           x * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x) * 0.39894228040143268f;
 }
 
 // ---- forward ------------------------------------------------------------------------------------------
-constexpr int MB = 256;
 
 __device__ __forceinline__ void load_weights(float *w, const uint16_t *__restrict__ wb) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) w[i] = bf16_f32(wb[i]);
     __syncthreads();
 }
 
-// Parameter i of the BF16 set, read as a 32-bit word holding parameters 2k, 2k+1 (little
-// endian): with i uniform over the wavefront the read is a scalar load and the weight a
-// scalar operand of the FMA, so the products need no LDS traffic at all.
-__device__ __forceinline__ float wparam(const uint32_t *__restrict__ w32, int i) {
-    const uint32_t u = w32[i >> 1];
-    return __uint_as_float((i & 1) ? (u & 0xffff0000u) : (u << 16));
+// Forward on the matrix cores.  Each layer is a product D = W H of the weights (outputs x
+// inputs) and the activations (inputs x points), taken 16 points at a time by one
+// wavefront with v_mfma_f32_16x16x4_f32 (FP32 operands and accumulation: the products and
+// sums are the FP32 ones of the definition, in another order).  Operand layouts of that
+// instruction on a wavefront, lane l = 16 kk + c (kk < 4, c < 16):
+//   A (16 x 4): lane l holds A[c][kk];  B (4 x 16): B[kk][c];
+//   D (16 x 16): 4 values, D[4 kk + r][c], r < 4.
+// So a lane holds, for point c of the block, outputs 4 kk + r of each 16-row tile q:
+// feature o = 16 q + 4 kk + r.  The next layer consumes them in place: its step (q, r)
+// takes from lane l the K slot kk = feature 16 q + 4 kk + r, and its A operand is the
+// weight column of that same feature, so activations never leave the registers.  The
+// weights (up to 64 per lane for W2) and biases are per-lane constants, loaded once per
+// wavefront; wavefronts walk the 16-point blocks.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int MB = 256;
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Point p: h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), y = W3 h2 + b3, one point per thread
-// (no loop over points: the weight loads would be hoisted out of it into more scalar
-// registers than there are).
-__global__ __launch_bounds__(MB) void k_mlp_fwd(const uint32_t *__restrict__ w32, const float *__restrict__ x9,
+__global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
                                                float *__restrict__ y6, long M, float in_inv, float out_scale) {
-    const long p = (long)blockIdx.x * MB + threadIdx.x;
-    if (p < M) {
-        float x[9];
+    const int lane = threadIdx.x & 63;
+    const int kk = lane >> 4, c = lane & 15;
+    auto w = [&](int i) { return bf16_f32(wb[i]); };
+    float a1[4][3], a2[4][16], a3[16];
+    v4f b1[4], b2[4], b3;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) x[c] = x9[c * M + p] * in_inv;
-        float h1[64];
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int o = 0; o < 64; ++o) {
-            float a = wparam(w32, OB1 + o);
+        for (int t = 0; t < 3; ++t) a1[q][t] = (4 * t + kk < 9) ? w(OW1 + (16 * q + c) * 9 + 4 * t + kk) : 0.f;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) a = fmaf(wparam(w32, OW1 + o * 9 + c), x[c], a);
-            h1[o] = gelu(a);
-        }
-        float y[6];
-#pragma unroll
-        for (int o = 0; o < 6; ++o) y[o] = wparam(w32, OB3 + o);
-#pragma unroll 2
-        for (int o = 0; o < 64; ++o) {
-            float a = wparam(w32, OB2 + o);
-#pragma unroll
-            for (int i = 0; i < 64; ++i) a = fmaf(wparam(w32, OW2 + o * 64 + i), h1[i], a);
-            const float h2 = gelu(a);
-#pragma unroll
-            for (int q = 0; q < 6; ++q) y[q] = fmaf(wparam(w32, OW3 + q * 64 + o), h2, y[q]);
+        for (int r = 0; r < 4; ++r) {
+            b1[q][r] = w(OB1 + 16 * q + 4 * kk + r);
+            b2[q][r] = w(OB2 + 16 * q + 4 * kk + r);
         }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) y6[q * M + p] = y[q] * out_scale;
+        for (int qi = 0; qi < 4; ++qi)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a2[q][4 * qi + r] = w(OW2 + (16 * q + c) * 64 + 16 * qi + 4 * kk + r);
+    }
+#pragma unroll
+    for (int qi = 0; qi < 4; ++qi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a3[4 * qi + r] = c < 6 ? w(OW3 + c * 64 + 16 * qi + 4 * kk + r) : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b3[r] = (4 * kk + r < 6) ? w(OB3 + 4 * kk + r) : 0.f;
+
+    const long nblk = (M + 15) / 16;
+    const long wv = (long)blockIdx.x * (MB / 64) + (threadIdx.x >> 6);
+    const long nwv = (long)gridDim.x * (MB / 64);
+    auto load_x = [&](long blk, float (&xv)[3]) {
+        const long p = blk * 16 + c;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int f = 4 * t + kk;
+            xv[t] = (blk < nblk && p < M && f < 9) ? x9[f * M + p] * in_inv : 0.f;
+        }
+    };
+    float xn[3];
+    load_x(wv, xn);
+    for (long blk = wv; blk < nblk; blk += nwv) {
+        float xv[3] = {xn[0], xn[1], xn[2]};
+        load_x(blk + nwv, xn);  // the next block's inputs, in flight during this block
+        v4f d1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d1[q] = b1[q];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) d1[q] = mfma4(a1[q][t], xv[t], d1[q]);
+        }
+        float h1[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h1[q][r] = gelu(d1[q][r]);
+        v4f d2[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d2[q] = b2[q];
+#pragma unroll
+            for (int qi = 0; qi < 4; ++qi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d2[q] = mfma4(a2[q][4 * qi + r], h1[qi][r], d2[q]);
+        }
+        // four independent accumulation chains (one per input tile), summed at the end
+        v4f d3q[4];
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            d3q[qi] = qi == 0 ? b3 : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d3q[qi] = mfma4(a3[4 * qi + r], gelu(d2[qi][r]), d3q[qi]);
+        }
+        const v4f d3 = (d3q[0] + d3q[1]) + (d3q[2] + d3q[3]);
+        const long p = blk * 16 + c;
+        if (p < M) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * kk + r < 6) y6[(4 * kk + r) * M + p] = d3[r] * out_scale;
+        }
     }
 }
 
@@ -411,10 +487,13 @@ static tk_status mlp_check(const tk_mlp *w) {
 }
 
 tk_status mlp_forward_run(const tk_mlp *w, const float *x9, float *y6, long M, hipStream_t s) {
-    if ((M + MB - 1) / MB > 0x7fffffffL) return fail(TK_EINVAL, "too many points (%ld)", M);
-    const unsigned nb = (unsigned)std::max<long>(1, (M + MB - 1) / MB);
-    hipLaunchKernelGGL(k_mlp_fwd, dim3(nb), dim3(MB), 0, s, (const uint32_t *)w->w, x9, y6, M, 1.0f / w->in_scale,
-                       w->out_scale);
+    // as many workgroups as are resident (each wavefront walks 16-point blocks), no more
+    // than there are blocks
+    const long nblk = (M + 15) / 16;
+    const long G = std::min<long>(resident_groups(reinterpret_cast<const void *>(&k_mlp_fwd), MB),
+                                  std::max<long>(1, (nblk + MB / 64 - 1) / (MB / 64)));
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)G), dim3(MB), 0, s, (const uint16_t *)w->w, x9, y6, M,
+                       1.0f / w->in_scale, w->out_scale);
     return launch_check("network forward");
 }
 
