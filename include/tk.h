@@ -274,7 +274,8 @@ tk_status rbc_destroy(tk_rbc_t rbc);
  * Ensembles: `count` independent FP32 solves of mixed grid sizes n[i] in {16, 24, 32,
  * 48, 64, 96, 128} with viscosities nu[i], advanced together by IF-RK2.  Every pass of
  * the right-hand side is one persistent kernel over a work list of all members' tiles
- * (largest grids first), and one step of all members is a single HIP-graph launch.
+ * (largest grids first), and one step of all members is a single HIP-graph launch (after
+ * one transform of the states per call: each step's last pass prepares the next step).
  * Each member's state has the single solver's layout.  flags >> 16, if nonzero, sets
  * the persistent grid size (workgroups; default 1024).
  * ------------------------------------------------------------------------------------ */

@@ -35,7 +35,7 @@ template <int N> struct BCfg {
 
 struct BInst {
     int n, K, KZC, KZP;  // KZP: transit row length (ns_kzp)
-    float2 *u, *w6, *aux, *ust;
+    float2 *u, *w6, *aux;  // state, transit workspace, RK accumulator (the stage input stays in registers)
     NsState *st;
     const float2 *tw;
     double nu;
@@ -58,17 +58,16 @@ static bool batch_size_ok(int n) {
 // kernel switching over every size took the largest size's registers for all of them).
 template <int N>
 __global__ __launch_bounds__(BNT) void kb_p1(const BInst *__restrict__ inst, const BItem *__restrict__ items,
-                                             int nitems, int stage2) {
+                                             int nitems) {
     __shared__ float2 smem[BCfg<N>::lds_x];
     float2 *tw = smem;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem w = items[it];
         const BInst &d = inst[w.inst];
-        const float2 *in = stage2 ? d.ust : d.u;
         __syncthreads();
         load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
         __syncthreads();
-        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(in, d.w6, d.K, stage2, w.tile, smem + N, tw);
+        ns_p1_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.u, d.w6, d.K, 0, w.tile, smem + N, tw);
     }
 }
 
@@ -105,23 +104,7 @@ __global__ __launch_bounds__(BNT) void kb_p3(const BInst *__restrict__ inst, con
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(BNT) void kb_p5(const BInst *__restrict__ inst, const BItem *__restrict__ items,
-                                             int nitems, int mode) {
-    __shared__ float2 smem[BCfg<N>::lds_x];
-    float2 *tw = smem;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const BItem w = items[it];
-        const BInst &d = inst[w.inst];
-        __syncthreads();
-        load_twiddles<float>(tw, d.tw, N, threadIdx.x, BNT);
-        __syncthreads();
-        ns_p5_tile<float, N, BCfg<N>::E, BCfg<N>::W>(d.w6, nullptr, d.u, d.aux, d.ust, nullptr, d.st, d.nu, mode,
-                                                     d.K, d.KZC, w.tile, smem + N, tw);
-    }
-}
-
-// P5 of the first stage fused with the second stage's P1 (the stage input stays in
+// P5 fused with the next right-hand side's P1 (the stage input, or the new state, stays in
 // registers; see ns_p5_tile).
 template <int N>
 __global__ __launch_bounds__(BNT) void kb_p51(const BInst *__restrict__ inst, const BItem *__restrict__ items,
@@ -158,18 +141,17 @@ __global__ void kb_set_h(const BInst *__restrict__ inst, int count, int n) {
 // The pass kernels of one size class.
 struct BClassFns {
     int n;
-    void (*p1)(const BInst *, const BItem *, int, int);
+    void (*p1)(const BInst *, const BItem *, int);
     void (*y)(const BInst *, const BItem *, int, int, int);
     void (*p3)(const BInst *, const BItem *, int, int);
-    void (*p5)(const BInst *, const BItem *, int, int);
     void (*p51)(const BInst *, const BItem *, int, int);
 };
 static BClassFns class_fns(int n) {
 #define TK_FNS(N) \
-    if (n == N) return {N, &kb_p1<N>, &kb_y<N>, &kb_p3<N>, &kb_p5<N>, &kb_p51<N>};
+    if (n == N) return {N, &kb_p1<N>, &kb_y<N>, &kb_p3<N>, &kb_p51<N>};
     TK_BATCH_SIZES(TK_FNS)
 #undef TK_FNS
-    return {0, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return {0, nullptr, nullptr, nullptr, nullptr};
 }
 
 // Tiles per instance of each pass.
@@ -236,9 +218,10 @@ static void nsb_free(tk_nsb_s *b) {
 }
 
 // One IF-RK2 step of every member as one graph: each size class runs its own chain of
-// passes (P1, Y, P3, step size, Y, P5 fused with the second stage's P1, then Y, P3, Y,
-// P5) on a stream of its own, forked from and joined to the capture stream, so the
-// classes' kernels overlap on the GPU.
+// passes (Y, P3, step size, Y, P5 fused with the second stage's P1, then Y, P3, Y, P5
+// fused with the next step's P1) on a stream of its own, forked from and joined to the
+// capture stream, so the classes' kernels overlap on the GPU.  On entry the workspace
+// holds P1 of the state (nsb_p1 before the first step of a call).
 static tk_status nsb_capture(tk_nsb_s *b) {
     const int nc = (int)b->cls_n.size();
     hipStream_t cs;
@@ -272,16 +255,13 @@ static tk_status nsb_capture(tk_nsb_s *b) {
         const auto &ni = b->nitems[c];
         auto g = [&](int list) { return (unsigned)std::max(1, std::min(b->grid, ni[list])); };
         for (int stage = 0; stage < 2; ++stage) {
-            if (stage == 0) hipLaunchKernelGGL(f.p1, dim3(g(4)), dim3(BNT), 0, q, b->dinst, it[4], ni[4], 0);
             hipLaunchKernelGGL(f.y, dim3(g(1)), dim3(BNT), 0, q, b->dinst, it[1], ni[1], 6, 1);
             hipLaunchKernelGGL(f.p3, dim3(g(2)), dim3(BNT), 0, q, b->dinst, it[2], ni[2], stage == 0);
             if (stage == 0)
                 hipLaunchKernelGGL(kb_set_h, dim3(cdiv(b->count, 64)), dim3(64), 0, q, b->dinst, b->count, f.n);
             hipLaunchKernelGGL(f.y, dim3(g(3)), dim3(BNT), 0, q, b->dinst, it[3], ni[3], 3, 0);
-            if (stage == 0)
-                hipLaunchKernelGGL(f.p51, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0], (int)RK2_S1);
-            else
-                hipLaunchKernelGGL(f.p5, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0], (int)RK2_S2);
+            hipLaunchKernelGGL(f.p51, dim3(g(0)), dim3(BNT), 0, q, b->dinst, it[0], ni[0],
+                               stage == 0 ? (int)RK2_S1 : (int)RK2_S2);
         }
         e = hipEventRecord(ev[c], q);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[c], 0);
@@ -302,6 +282,17 @@ static tk_status nsb_capture(tk_nsb_s *b) {
     }
     b->graph = gr;
     return TK_OK;
+}
+
+// P1 of every member's state into its workspace (before the first step of a call).
+static tk_status nsb_p1(tk_nsb_s *b, hipStream_t s) {
+    for (size_t c = 0; c < b->cls_n.size(); ++c) {
+        const BClassFns f = class_fns(b->cls_n[c]);
+        const int ni = b->nitems[c][4];
+        const unsigned g = (unsigned)std::max(1, std::min(b->grid, ni));
+        hipLaunchKernelGGL(f.p1, dim3(g), dim3(BNT), 0, s, b->dinst, b->items[c][4], ni);
+    }
+    return launch_check("ensemble P1");
 }
 
 extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, const double *nu, tk_dtype dt,
@@ -333,20 +324,16 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
             return st;
         }
         const size_t fb = (size_t)n[i] * n[i] * (n[i] / 2 + 1) * sizeof(float2);
-        void *w6 = nullptr, *aux = nullptr, *ust = nullptr;
-        if (hipMalloc(&w6, 6 * fb) != hipSuccess || hipMalloc(&aux, 3 * fb) != hipSuccess ||
-            hipMalloc(&ust, 3 * fb) != hipSuccess) {
+        void *w6 = nullptr, *aux = nullptr;
+        if (hipMalloc(&w6, 6 * fb) != hipSuccess || hipMalloc(&aux, 3 * fb) != hipSuccess) {
             if (w6) hipFree(w6);
-            if (aux) hipFree(aux);
             nsb_free(b);
             return fail(TK_ENOMEM, "ensemble workspace allocation failed");
         }
         b->bufs.push_back(w6);
         b->bufs.push_back(aux);
-        b->bufs.push_back(ust);
-        // stage buffers start at zero: passes write only the 2/3-rule modes
-        if (hipMemset(aux, 0, 3 * fb) != hipSuccess || hipMemset(ust, 0, 3 * fb) != hipSuccess ||
-            hipMemset(w6, 0, 6 * fb) != hipSuccess) {
+        // the accumulator starts at zero: passes write only the 2/3-rule modes
+        if (hipMemset(aux, 0, 3 * fb) != hipSuccess || hipMemset(w6, 0, 6 * fb) != hipSuccess) {
             nsb_free(b);
             return fail(TK_EHIP, "ensemble workspace clear failed");
         }
@@ -358,7 +345,6 @@ extern "C" tk_status ns_batch_create(tk_nsb_t *out, int count, const int *n, con
         d.u = nullptr;
         d.w6 = (float2 *)w6;
         d.aux = (float2 *)aux;
-        d.ust = (float2 *)ust;
         d.tw = (const float2 *)b->grids[i].ax.twx;
         d.nu = nu[i];
         maxshell = std::max(maxshell, ns_num_shells(n[i]));
@@ -426,6 +412,7 @@ extern "C" tk_status ns_batch_step(tk_nsb_t b, void *const *uhat, double dt, int
     }
     TK_HIP_CHECK(hipMemcpyAsync(b->dinst, b->hinst.data(), sizeof(BInst) * b->count, hipMemcpyHostToDevice, s));
     TK_HIP_CHECK(hipMemcpyAsync(b->dstate, b->hstate.data(), sizeof(NsState) * b->count, hipMemcpyHostToDevice, s));
+    if (nsteps > 0) TK_TRY(nsb_p1(b, s));
     for (int k = 0; k < nsteps; ++k) TK_HIP_CHECK(hipGraphLaunch(b->gexec, s));
     TK_HIP_CHECK(hipMemcpyAsync(b->hstate.data(), b->dstate, sizeof(NsState) * b->count, hipMemcpyDeviceToHost, s));
     TK_HIP_CHECK(hipStreamSynchronize(s));

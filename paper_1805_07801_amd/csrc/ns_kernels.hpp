@@ -701,16 +701,24 @@ template <typename C> __global__ void k_zero(C *p, long n) {
 }
 
 // ---- instantiation helpers --------------------------------------------------------------------------
-// Tile shapes.  P1/P5 hold three fields per thread, so their workgroups stay at <= 512
-// threads (the compiler caps 1024-thread workgroups at 64 VGPRs and spills): E points per
-// thread (doubled for FP32 lines >= 256) and W columns (16 for FP32, 8 for FP64, fewer if
-// that would exceed 512 threads).  P3 uses E = default_E(N/2) and 256 threads.
-template <typename T> constexpr int ns_x_E(int N) { return (sizeof(T) == 4 && N >= 256) ? 2 * default_E(N) : default_E(N); }
+// Tile shapes of P1 / P5 / the fused P5+P1: E = default_E(N) points per thread and W
+// columns (16 for FP32, 8 for FP64, fewer if the workgroup would exceed its thread cap).
+// They hold three fields per thread; a 1024-thread workgroup (4 waves per SIMD) leaves 128
+// registers per thread, enough at E <= 8 in FP32 (about 112), so the cap is 1024 threads
+// there and 512 otherwise.  The convection passes hold a fourth field and keep 512
+// (ns_rbc_W).  P3 uses E = default_E(N/2) and 256 threads.
+template <typename T> constexpr int ns_x_E(int N) { return default_E(N); }
+template <typename T> constexpr int ns_x_cap(int N) { return (sizeof(T) == 4 && ns_x_E<T>(N) <= 8) ? 1024 : 512; }
 template <typename T> constexpr int ns_x_W(int N) {
     int E = ns_x_E<T>(N);
     int W = sizeof(T) == 8 ? 8 : 16;
-    while (W > 1 && W * (N / E) > 512) W /= 2;
+    while (W > 1 && W * (N / E) > ns_x_cap<T>(N)) W /= 2;
     while (W * (N / E) < 64) W *= 2;
+    return W;
+}
+template <typename T> constexpr int ns_rbc_W(int N) {
+    int W = ns_x_W<T>(N);
+    while (W > 1 && W * (N / ns_x_E<T>(N)) > 512) W /= 2;
     return W;
 }
 constexpr int ns_z_LPW(int N) {
@@ -773,14 +781,13 @@ void launch_ns_p51(const P5Args &a, int K, int KZC, const void *tw, hipStream_t 
                        (const V2<T> *)tw);
 }
 
-// Column-pass variant (E, W) of P1 / P5 (FP32, N >= 128): kept when it differs from the
-// default, W is whole, the workgroup has 64..1024 threads and the LDS tile fits.  Both get
-// 512- and 1024-thread tiles of E = default_E(N) (a 1024-thread workgroup leaves 128
-// registers per thread, enough for P1's three input fields at E = 8).  (Persistent P1
-// workgroups loading the next tile ahead measured 1.5x slower at 512^3.)
+// Column-pass variant (E, W) of P1 / P5 / P5+P1 (FP32, N >= 128): kept when it differs
+// from the default, W is whole, the workgroup has 64 threads up to the cap of ns_x_cap
+// and the LDS tile fits; the 512- and 1024-thread tiles of E = default_E(N) are offered.
+// (Persistent P1 workgroups loading the next tile ahead measured 1.5x slower at 512^3.)
 template <typename T, int N, int E, int W> constexpr bool ns_x_var_ok() {
     return sizeof(T) == 4 && N >= 128 && E <= N && N % E == 0 && rplan_ok(N, E) && W >= 1 &&
-           W * (N / E) >= 64 && W * (N / E) <= 1024 && (long)(N * (W + 1) + N) * 2 * (long)sizeof(T) <= 163840 &&
+           W * (N / E) >= 64 && W * (N / E) <= ns_x_cap<T>(N) && (long)(N * (W + 1) + N) * 2 * (long)sizeof(T) <= 163840 &&
            !(E == ns_x_E<T>(N) && W == ns_x_W<T>(N));
 }
 template <typename T, int N, int E, int W> void add_ns_p1_var(NsKernels &k) {
@@ -828,10 +835,11 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     add_ns_p5_var<T, N, Ed, 512 * Ed / N>(k);
     add_ns_p5_var<T, N, Ed, 1024 * Ed / N>(k);
     add_ns_z_var<T, N, default_E(L2) / 2>(k);
+    constexpr int Wr = ns_rbc_W<T>(N);
     k.p1r = [](const void *u, void *w7, int K, int KZC, const void *tw, double ka, hipStream_t s) {
         // the convection solver keeps its stage buffers in the state layout
         const long ncols = (long)(2 * K + 1) * ns_kzp<N>();
-        hipLaunchKernelGGL((k_ns_p1<T, N, E, W, true>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+        hipLaunchKernelGGL((k_ns_p1<T, N, E, Wr, true>), dim3(cdiv(ncols, Wr)), dim3(Wr * (N / E)), 0, s,
                            (const V2<T> *)u, (V2<T> *)w7, K, 0, (const V2<T> *)tw, (T)ka);
     };
     k.p3r = [](void *w7, long nlines, int KZC, const void *tw, float *part, hipStream_t s) {
@@ -841,7 +849,7 @@ template <typename T, int N> NsKernels make_ns_kernels() {
     k.p5r = [](const void *c6, const void *uin, void *u, void *aux, void *ust, void *out, const NsState *st,
                double nu_a, double kap_a, double ka, int mode, int K, int KZC, const void *tw, hipStream_t s) {
         const long ncols = (long)(2 * K + 1) * KZC;
-        hipLaunchKernelGGL((k_rbc_p5<T, N, E, W>), dim3(cdiv(ncols, W)), dim3(W * (N / E)), 0, s,
+        hipLaunchKernelGGL((k_rbc_p5<T, N, E, Wr>), dim3(cdiv(ncols, Wr)), dim3(Wr * (N / E)), 0, s,
                            (const V2<T> *)c6, (const V2<T> *)uin, (V2<T> *)u, (V2<T> *)aux, (V2<T> *)ust,
                            (V2<T> *)out, st, nu_a, kap_a, (T)ka, mode, K, KZC, (const V2<T> *)tw);
     };
