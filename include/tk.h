@@ -71,6 +71,8 @@ tk_status tk_sum_squares(const void *x, long n, tk_dtype dt, double *out, void *
 #define TK_FFT_TIMING 0x1u    /* record per-pass HIP events (fft3d_pass_times) */
 #define TK_FFT_NO_TUNE 0x2u   /* ignore the autotuner cache, use default tiles */
 #define TK_FFT_C2R_Y_FIRST 0x4u /* c2r: inverse Y (out of place) before X (in place); same result */
+#define TK_FFT_C2R_OVERWRITE 0x8u /* c2r may overwrite cplx_in: X and Y inverses in place on it, no
+                                     workspace (FFTW's default for c2r); same result */
 
 /* Create a plan for `batch` fields of nx*ny*nz points in dtype dt.  Allocates twiddle
  * tables (a few KB) on the current device.  Sizes must be supported (see above);
@@ -105,7 +107,8 @@ tk_status fft3d_set_workspace(tk_fft3d_t plan, void *dev_ptr);
 tk_status fft3d_r2c(tk_fft3d_t plan, const void *real_in, void *cplx_out, void *stream);
 
 /* Inverse c2r, unscaled: cplx_in -> real_out.  cplx_in is preserved (the solver needs
- * its spectral state intact).  On the kz = 0 and kz = nz/2 planes only the Hermitian
+ * its spectral state intact) unless the plan has TK_FFT_C2R_OVERWRITE, which leaves it
+ * holding the partial (X- and Y-inverted) transform.  On the kz = 0 and kz = nz/2 planes only the Hermitian
  * part matters: the result is sum_{kz} w(kz) Re[sum_{kx,ky} F(k) exp(i k.x)] with
  * w = 1 on those planes and 2 elsewhere. */
 tk_status fft3d_c2r(tk_fft3d_t plan, const void *cplx_in, void *real_out, void *stream);

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libtk.so")
 
 TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ESTATE = 0, -1, -2, -3, -4, -5
 TK_F32, TK_F64 = 0, 1
-TK_FFT_TIMING, TK_FFT_NO_TUNE, TK_FFT_C2R_Y_FIRST = 0x1, 0x2, 0x4
+TK_FFT_TIMING, TK_FFT_NO_TUNE, TK_FFT_C2R_Y_FIRST, TK_FFT_C2R_OVERWRITE = 0x1, 0x2, 0x4, 0x8
 
 _lib = None
 

@@ -197,6 +197,10 @@ extern "C" tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz,
     if (!plan) return fail(TK_EINVAL, "plan is NULL");
     *plan = nullptr;
     if (batch < 1) return fail(TK_EINVAL, "batch must be >= 1 (got %d)", batch);
+    const unsigned known = TK_FFT_TIMING | TK_FFT_NO_TUNE | TK_FFT_C2R_Y_FIRST | TK_FFT_C2R_OVERWRITE;
+    if (flags & ~known) return fail(TK_EINVAL, "unknown plan flags 0x%x", flags & ~known);
+    if ((flags & TK_FFT_C2R_Y_FIRST) && (flags & TK_FFT_C2R_OVERWRITE))
+        return fail(TK_EINVAL, "TK_FFT_C2R_Y_FIRST and TK_FFT_C2R_OVERWRITE exclude each other");
     tk_fft3d_s *p = new (std::nothrow) tk_fft3d_s();
     if (!p) return fail(TK_ENOMEM, "host allocation failed");
     tk_status st = axes_init(&p->ax, nx, ny, nz, dt, !(flags & TK_FFT_NO_TUNE));
@@ -273,6 +277,24 @@ extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out
 extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out, void *stream) {
     if (!p || !cplx_in || !real_out) return fail(TK_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    const FftAxes &ax0 = p->ax;
+    if (p->flags & TK_FFT_C2R_OVERWRITE) {
+        // in place on the input: X backwards (the forward X pass wrote those columns last),
+        // Y, then Z backwards into the output
+        hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
+        void *w = const_cast<void *>(cplx_in);
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
+        TK_TRY(fft_x_pass(ax0, w, w, p->batch, 1, 1.0, s, 1));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_y_pass(ax0, w, w, p->batch, 1, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
+        TK_TRY(fft_z_c2r(ax0, w, real_out, p->batch, s, 1));
+        if (ev) {
+            TK_HIP_CHECK(hipEventRecord(ev[7], s));
+            p->nc2r++;
+        }
+        return TK_OK;
+    }
     if (!p->ws) {
         if (hipMalloc(&p->ws, cplx_bytes(p)) != hipSuccess) {
             p->ws = nullptr;

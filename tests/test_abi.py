@@ -63,3 +63,13 @@ def test_solver_entry_points_reject_null_handles(lib):
     assert lib.ns_step(None, None, 0.1, 1, None, None) == tk.TK_EINVAL
     assert lib.ns_rhs(None, None, None, None) == tk.TK_EINVAL
     assert lib.ns_destroy(None) == tk.TK_OK
+
+
+def test_plan_rejects_unknown_and_conflicting_flags(lib):
+    import paper_1805_07801_amd as tk
+    h = ctypes.c_void_p()
+    assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 1, tk.TK_F32, 0x100) == tk.TK_EINVAL
+    assert b"unknown plan flags" in lib.tk_last_error()
+    both = tk.TK_FFT_C2R_Y_FIRST | tk.TK_FFT_C2R_OVERWRITE
+    assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 1, tk.TK_F32, both) == tk.TK_EINVAL
+    assert h.value is None

@@ -171,3 +171,24 @@ def test_two_1024_members_split_per_plane(tk):
     assert err <= TOL["f32"]
     p1.close()
     p2.close()
+
+
+@pytest.mark.parametrize("shape,basis", [((64, 64, 64), (0, 0)), ((512, 512, 512), (0, 0)), ((48, 32, 24), (1, 2))])
+def test_c2r_overwrite_equals_preserving_c2r(tk, shape, basis):
+    """TK_FFT_C2R_OVERWRITE runs the same passes in place on the input: the real output
+    equals the preserving plan's bit for bit."""
+    import torch
+    nx, ny, nz = shape
+    g = torch.Generator(device="cuda").manual_seed(nx + ny)
+    x = torch.randn((1, nx, ny, nz), generator=g, device="cuda", dtype=torch.float32)
+    kw = {} if basis == (0, 0) else {"basis_x": basis[0], "basis_y": basis[1]}
+    p0 = tk.FFT3D(nx, ny, nz, dtype=torch.float32, **kw)
+    p1 = tk.FFT3D(nx, ny, nz, dtype=torch.float32, flags=tk.TK_FFT_C2R_OVERWRITE, **kw)
+    X = p0.r2c(x)
+    y0 = p0.c2r(X)
+    Xc = X.clone()
+    y1 = p1.c2r(Xc)
+    assert torch.equal(y0, y1)
+    assert not torch.equal(Xc, X)  # the input was used as workspace
+    p0.close()
+    p1.close()
