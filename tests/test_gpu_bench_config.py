@@ -1,0 +1,55 @@
+"""The benchmark's own launch configuration at its full sizes against the FP64 oracle:
+the committed autotuner cache, the pair's plan flags (c2r using its input as workspace)
+and the solver's fused CFL stepper at 512^3."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import diag, fft as offt, ns as ons
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fft_pair_512_with_bench_plan(tk):
+    import torch
+    from paper_1805_07801_amd import tune
+    n = 512
+    try:
+        assert tune.load_default() > 0
+        f = synth.gaussian_field((1, n, n, n), 0)  # N(0,1), seed 0, as timed
+        plan = tk.FFT3D(n, dtype=torch.float32, flags=tk.TK_FFT_TIMING | tk.TK_FFT_C2R_OVERWRITE)
+        x = torch.from_numpy(f).cuda()
+        X = plan.r2c(x)
+        Xn = X.cpu().numpy()[0]
+        assert diag.rel_l2(Xn, offt.rfft3(f[0].astype(np.float64)), n) <= 1e-5
+        gref = offt.irfft3(Xn.astype(np.complex128), n)
+        y = plan.c2r(X)  # X is used as workspace
+        assert diag.rel_l2(y.cpu().numpy()[0], gref) <= 1e-5
+        assert diag.rel_l2(y.cpu().numpy(), f) <= 1e-5
+        plan.close()
+    finally:
+        tk.tune_clear()
+
+
+def test_ns_512_cfl_step_with_bench_config(tk):
+    """One IF-RK2 step, CFL 0.5, nu 1e-3, of the decaying-turbulence initial field (seed 1),
+    tuned tiles, the fused stepper; both sides start from the GPU's initial state (its own
+    parity with the oracle is test_rhs_512_vs_oracle's)."""
+    import torch
+    from paper_1805_07801_amd import tune
+    n = 512
+    try:
+        assert tune.load_default() > 0
+        noise = synth.gaussian_field((3, n, n, n), 1)
+        s = tk.NS(n, dtype=torch.float32, nu=1e-3, cfl=0.5)
+        ud = s.init_random(torch.from_numpy(noise).cuda())
+        del noise
+        u = ud.cpu().numpy().astype(np.complex128)
+        s.step(ud, 0.0, 1)
+        h_ref = ons.cfl_dt(u, 0.5)
+        assert abs(s.last_dt() - h_ref) <= 1e-5 * h_ref
+        ref = ons.ifrk2_step(u, 1e-3, h_ref)[0]
+        assert diag.rel_l2(ud.cpu().numpy(), ref, n) <= 1e-4
+        s.close()
+    finally:
+        tk.tune_clear()
