@@ -296,6 +296,75 @@ def ns_steps_per_s(tk, torch, n, steps, warmup):
     return steps / dt, e, passes
 
 
+def extension_rates(tk, torch, n=512):
+    """The rows built beyond the hot path, each at 512^3 FP32: IF-RK4 steps/s of the
+    decaying-turbulence field (CFL 0.5), Rayleigh-Benard (FFF) IF-RK2 steps/s, the
+    sine-basis (SFF) transform pair, and the energy-transfer diagnostics."""
+    import synth
+    out = {}
+    noise = torch.from_numpy(synth.gaussian_field((3, n, n, n), 1)).cuda()
+    ns = tk.NS(n, dtype=torch.float32, nu=1e-3, cfl=0.5, scheme="rk4")
+    u = ns.init_random(noise)
+    del noise
+    ns.step(u, 0.0, 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ns.step(u, 0.0, 10)
+    torch.cuda.synchronize()
+    out["ns512_rk4_steps_per_s"] = round(10 / (time.perf_counter() - t), 2)
+    # energy transfer T(s) and a 4-band shell-to-shell matrix of the same state
+    nsh = tk.num_shells(n)
+    ns.energy_transfer(u)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        ns.energy_transfer(u)
+    torch.cuda.synchronize()
+    out["transfer512_ms"] = round((time.perf_counter() - t) / 3 * 1e3, 2)
+    bands = [min(3, s // 8) for s in range(nsh)]
+    t = time.perf_counter()
+    ns.shell_to_shell(u, bands, 4)
+    torch.cuda.synchronize()
+    out["shell_to_shell512_4bands_ms"] = round((time.perf_counter() - t) * 1e3, 2)
+    ns.close()
+    del u
+    # convection: random small state (u, theta), Ra 1e6, Pr 1
+    rbc = tk.RBC(n, Ra=1e6, Pr=1.0)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    s4 = (torch.randn((4, n, n, n // 2 + 1), generator=g, device="cuda", dtype=torch.complex64) * 1e-6).contiguous()
+    rbc.step(s4, 1e-4, 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rbc.step(s4, 1e-4, 10)
+    torch.cuda.synchronize()
+    out["rbc512_rk2_steps_per_s"] = round(10 / (time.perf_counter() - t), 2)
+    del s4, rbc
+    # sine basis along x (SFF): r2c + c2r pair
+    plan = tk.FFT3D(n, dtype=torch.float32, basis_x=1)
+    x = torch.randn((1, n, n, n), generator=g, device="cuda", dtype=torch.float32)
+    X = plan.empty_cplx()
+    y = plan.empty_real()
+    for _ in range(3):
+        plan.r2c(x, X)
+        plan.c2r(X, y)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(10):
+        plan.r2c(x, X)
+        plan.c2r(X, y)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 10
+    R, C = field_bytes(n)
+    out["sff512_pair_ms"] = round(ms, 4)
+    out["sff512_pair_GBps"] = round((2 * R + 10 * C) / (ms * 1e-3) / 1e9, 1)
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def tg32_steps_per_s(tk, torch, steps=200):
     """Steps/s of the 32^3 FP64 Taylor-Green configuration (nu 0.01, fixed dt 0.01, IF-RK2):
     launch/latency-bound, one graph launch per step."""
@@ -397,6 +466,7 @@ def main():
         out["ns512_passes"] = nsp
         out["tg32_fp64_rk2_steps_per_s"] = round(tg32_steps_per_s(tk, torch), 1)
     if not args.no_extra:
+        out.update(extension_rates(tk, torch))
         out.update(ensemble_rate(tk, torch))
         out.update(les_rate(tk, torch))
         if "ns512_rk2_steps_per_s" in out:
