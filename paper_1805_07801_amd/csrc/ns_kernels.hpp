@@ -370,7 +370,7 @@ struct P5Args {
     const void *c3;    // 3 fields after P4 (transit layout)
     const void *add3;  // optional extra term added before masking/projection (spectral, scaled), or null
     void *u;           // state (read; written by RK2_S2 / RK4_S4)
-    void *aux;         // RK2: N^n; RK4: accumulator (transit layout)
+    void *aux;         // RK accumulator (transit layout): every term of the new state but the last stage's
     void *ust;         // stage input written by the first stages (transit layout)
     void *out;         // NS_RHS output
     const NsState *st;
