@@ -94,7 +94,8 @@ tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz, int batch,
 tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt, int basis_x,
                                   int basis_y, unsigned flags);
 
-/* Bytes of device workspace fft3d_c2r needs (one spectral field per batch member). */
+/* Bytes of device workspace fft3d_c2r needs (one spectral field per batch member; none
+ * with TK_FFT_C2R_OVERWRITE). */
 tk_status fft3d_workspace_size(tk_fft3d_t plan, size_t *bytes);
 
 /* Supply caller-owned device workspace of at least fft3d_workspace_size bytes (NULL

@@ -241,7 +241,7 @@ extern "C" tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, i
 
 extern "C" tk_status fft3d_workspace_size(tk_fft3d_t p, size_t *bytes) {
     if (!p || !bytes) return fail(TK_EINVAL, "NULL argument");
-    *bytes = cplx_bytes(p);
+    *bytes = (p->flags & TK_FFT_C2R_OVERWRITE) ? 0 : cplx_bytes(p);
     return TK_OK;
 }
 

@@ -190,5 +190,9 @@ def test_c2r_overwrite_equals_preserving_c2r(tk, shape, basis):
     y1 = p1.c2r(Xc)
     assert torch.equal(y0, y1)
     assert not torch.equal(Xc, X)  # the input was used as workspace
+    import ctypes
+    sz = ctypes.c_size_t()
+    assert tk.lib().fft3d_workspace_size(p1.h, ctypes.byref(sz)) == tk.TK_OK and sz.value == 0
+    assert tk.lib().fft3d_workspace_size(p0.h, ctypes.byref(sz)) == tk.TK_OK and sz.value == X.numel() * 8
     p0.close()
     p1.close()
