@@ -419,12 +419,14 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *c3, const V2<T> *__restr
     // transit-layout fields (c3, aux, ust)
     const unsigned lo = (unsigned)((row * NZH + kz + (long)jt * RS) * (long)sizeof(C));
     const unsigned loc = (unsigned)((row * KZP + kz + (long)jt * RSc) * (long)sizeof(C));
+    // Unguarded loads: a lane past the last column addresses column 0 (row = kz = 0 above),
+    // transforms it and stores nothing.  Without a select on the loaded values the first
+    // transform waits for its own field's loads only, not for all three fields'.
     C cf[3][E];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
 #pragma unroll
-        for (int i = 0; i < E; ++i)
-            cf[f][i] = valid ? *at_bytes(c3 + f * FSc + (long)(i * TPL) * RSc, loc) : mk<T>(0, 0);
+        for (int i = 0; i < E; ++i) cf[f][i] = *at_bytes(c3 + f * FSc + (long)(i * TPL) * RSc, loc);
     }
     // unrolled over the fields: a run-time field index into cf would put it in scratch
 #pragma unroll
