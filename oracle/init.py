@@ -39,3 +39,16 @@ def random_solenoidal(noise, energy=1.0):
     uhat = uhat * factor[s][None]
     e = diag.energy(uhat)
     return uhat * np.sqrt(energy / e)
+
+
+def band_filling(noise, energy=1.0):
+    """A solenoidal spectral velocity whose every kept mode carries O(1) of the typical
+    mode amplitude (flat per mode, E(s) growing as s^2 up to the 2/3 cutoff), for parity
+    checks that must see the whole kept band:
+      1. r2c of the noise; 2. projection; 3. 2/3 mask and k = 0 removed;
+      4. total energy normalised to ``energy``."""
+    n = noise.shape[-3]
+    uhat = ns.project(fft.rfft3(np.asarray(noise, dtype=np.float64)))
+    uhat = uhat * ns.dealias_mask(n)
+    uhat[:, 0, 0, 0] = 0.0
+    return uhat * np.sqrt(energy / diag.energy(uhat))

@@ -60,7 +60,8 @@ def sgs_stress(uhat_dns, n_les, kc):
 
 
 def closure_tau(theta, ubar_hat, in_scale, out_scale):
-    """Stress the network predicts from the filtered state: out_scale * f(grad / in_scale)."""
+    """Stress the network predicts from the filtered state: the nine gradient features
+    are divided by in_scale, and the six network outputs multiplied by out_scale."""
     g = gradients(ubar_hat)
     n = g.shape[-1]
     y = mlp.forward(theta, g.reshape(9, -1) / in_scale)
@@ -77,14 +78,23 @@ def sgs_divergence(tau):
     return np.stack([-1j * (k[0] * T[i][0] + k[1] * T[i][1] + k[2] * T[i][2]) for i in range(3)])
 
 
-def les_rhs(ubar_hat, theta, in_scale, out_scale):
-    """N_LES = P M [F(u x omega) - i k_j tau^_ij]."""
+def les_rhs_tau(ubar_hat, tau):
+    """N_LES = P M [F(u x omega) - i k_j tau^_ij] for a given real-space stress tau
+    [6][n][n][n] (None: no model term).  The filtered momentum equation: the resolved
+    nonlinear term of eq:NSk plus the divergence of the sub-grid stress, which enters
+    with the same sign as the resolved flux -i k_j (u_i u_j)^."""
     n = ubar_hat.shape[-3]
     what = ns.curl(ubar_hat)
     u = fft.irfft3(ubar_hat)
     w = fft.irfft3(what)
     c = np.stack([u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]])
     chat = fft.rfft3(c)
-    if theta is not None:
-        chat = chat + sgs_divergence(closure_tau(theta, ubar_hat, in_scale, out_scale))
+    if tau is not None:
+        chat = chat + sgs_divergence(tau)
     return ns.project(chat * ns.dealias_mask(n))
+
+
+def les_rhs(ubar_hat, theta, in_scale, out_scale):
+    """LES right-hand side with the network's stress (theta None: plain right-hand side)."""
+    tau = None if theta is None else closure_tau(theta, ubar_hat, in_scale, out_scale)
+    return les_rhs_tau(ubar_hat, tau)

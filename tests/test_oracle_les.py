@@ -159,3 +159,87 @@ def test_les_rhs_without_model_is_plain_rhs():
     th = rand_theta(1, scale=0.0)  # zero weights, zero-ish biases -> constant stress -> no divergence
     th[:] = 0
     assert np.max(np.abs(les.les_rhs(uh, th, 1.0, 1.0) - ns.rhs(uh))) <= 1e-18
+
+
+def band_filling_state(n, seed):
+    return init.band_filling(synth.gaussian_field((3, n, n, n), seed))
+
+
+@pytest.mark.parametrize("n_dns,n_les,kc", [(48, 24, 7), (96, 64, 21)])
+def test_les_rhs_with_true_stress_is_truncated_dns_rhs(n_dns, n_les, kc):
+    """Filtered-DNS identity (the sharp box G is the coarse grid's 2/3 set, and both
+    grids are alias-free after their masks): the LES right-hand side of ubar = G u with
+    the exact stress tau = G(u_i u_j) - G(ubar_i ubar_j) is the DNS right-hand side
+    truncated to |k_i| <= kc, to round-off.  A flipped sign of the stress term, or the
+    stress taken unfiltered, breaks it."""
+    uh = band_filling_state(n_dns, seed=n_dns + 3)
+    ref = les.truncate(ns.rhs(uh), n_les, kc)
+    ub = les.filtered_velocity(uh, n_les, kc)
+    tau = les.sgs_stress(uh, n_les, kc)
+    got = les.les_rhs_tau(ub, tau)
+    assert diag.rel_l2(got, ref, n_les) <= 1e-13
+    # the model term matters: without it (or with its sign flipped) the identity fails
+    assert diag.rel_l2(les.les_rhs_tau(ub, None), ref, n_les) >= 0.05
+    assert diag.rel_l2(les.les_rhs_tau(ub, -tau), ref, n_les) >= 0.1
+    # les_rhs with a network routes through the same expression
+    th = rand_theta(2)
+    t_net = les.closure_tau(th, ub, 3.0, 0.5)
+    assert np.array_equal(les.les_rhs(ub, th, 3.0, 0.5), les.les_rhs_tau(ub, t_net))
+
+
+def eddy_viscosity_theta(c=1.0):
+    """Network weights whose output is exactly linear in the inputs for |x| << 1000:
+    layer 1 copies the 9 inputs shifted by +1000 (GELU is the identity there in FP64),
+    layer 2 is the identity, layer 3 forms y_ij = -c (x_ij + x_ji) and removes the shift
+    (every weight is a BF16 value).  With x = grad ubar / in_scale and tau = out_scale y
+    this is the eddy-viscosity stress tau = -2 nu_t S, nu_t = c out_scale / in_scale."""
+    W1 = np.zeros((64, 9))
+    W1[np.arange(9), np.arange(9)] = 1.0
+    b1 = np.zeros(64)
+    b1[:9] = 1000.0
+    W2 = np.eye(64)
+    b2 = np.zeros(64)
+    W3 = np.zeros((6, 64))
+    # feature 3 i + j is d_j ubar_i; outputs xx, yy, zz, xy, xz, yz
+    for o, (i, j) in enumerate(les.PAIRS):
+        W3[o, 3 * i + j] -= c
+        W3[o, 3 * j + i] -= c
+    b3 = -1000.0 * W3.sum(axis=1)
+    th = mlp.pack([W1, W2, W3], [b1, b2, b3])
+    assert np.array_equal(mlp.bf16_round(th), th)
+    return th
+
+
+def test_closure_eddy_viscosity_closed_form():
+    """With the eddy-viscosity network, -i k_j tau^_ij = -nu_t |k|^2 u^ for a solenoidal
+    field, so the LES right-hand side is the plain one minus nu_t |k|^2 u^: this fixes the
+    sign of the model term, where in_scale and out_scale apply (nu_t = out/in, not in/out),
+    and the order of the network's input and output components."""
+    n = 24
+    ub = band_filling_state(n, seed=11)
+    in_scale, out_scale = 4.0, 0.5
+    nu_t = out_scale / in_scale
+    th = eddy_viscosity_theta()
+    tau = les.closure_tau(th, ub, in_scale, out_scale)
+    S = les.gradients(ub).reshape(3, 3, n, n, n)
+    for o, (i, j) in enumerate(les.PAIRS):
+        assert np.max(np.abs(tau[o] + nu_t * (S[i, j] + S[j, i]))) <= 1e-10
+    got = les.les_rhs(ub, th, in_scale, out_scale)
+    ref = ns.rhs(ub) - nu_t * ns.k_squared(n) * ub
+    assert diag.rel_l2(got, ref, n) <= 1e-11
+    assert diag.rel_l2(got, ns.rhs(ub), n) >= 0.1
+
+
+def test_closure_scale_conventions():
+    """tau = out_scale f(grad / in_scale): doubling out_scale doubles tau; scaling the
+    filtered field and in_scale by the same factor leaves tau unchanged."""
+    n = 16
+    ub = band_filling_state(n, seed=12)
+    th = rand_theta(5)
+    t1 = les.closure_tau(th, ub, 2.0, 0.25)
+    assert np.max(np.abs(les.closure_tau(th, ub, 2.0, 0.5) - 2.0 * t1)) <= 1e-15 * np.max(np.abs(t1)) * 4
+    t3 = les.closure_tau(th, 3.0 * ub, 6.0, 0.25)
+    assert np.max(np.abs(t3 - t1)) <= 1e-12 * np.max(np.abs(t1))
+    # the network is not linear: scaling the field alone changes tau by more than the factor
+    t4 = les.closure_tau(th, 3.0 * ub, 2.0, 0.25)
+    assert np.max(np.abs(t4 - 3.0 * t1)) >= 1e-3 * np.max(np.abs(t1))
