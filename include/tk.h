@@ -114,6 +114,23 @@ tk_status fft3d_r2c(tk_fft3d_t plan, const void *real_in, void *cplx_out, void *
  * w = 1 on those planes and 2 elsewhere. */
 tk_status fft3d_c2r(tk_fft3d_t plan, const void *cplx_in, void *real_out, void *stream);
 
+/* Bytes of the static device scratch fft3d_c2r_noalloc uses as its workspace (80 MiB: a
+ * 256^3 FP32 or 192^3 FP64 half spectrum fits). */
+#define TK_SCRATCH_BYTES (80u << 20)
+
+/* As fft3d_c2r (same passes, same result, input preserved), but allocation-free: for
+ * callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The workspace is a static device
+ * array of TK_SCRATCH_BYTES that every device running this library holds until the
+ * process ends; its address is looked up once per device on the first call there.  The
+ * call allocates nothing and needs no clearing (the first pass overwrites the whole
+ * workspace).  Plans whose spectral field (times batch) exceeds TK_SCRATCH_BYTES get
+ * TK_EINVAL with nothing queued.  All calls on one device share the one array: calls
+ * that may overlap in time on one device (several streams, several host threads) race
+ * and must be serialised by the caller.  Plans with TK_FFT_C2R_OVERWRITE need no
+ * workspace and behave exactly as fft3d_c2r. */
+tk_status fft3d_c2r_noalloc(tk_fft3d_t plan, const void *cplx_in, void *real_out, void *stream);
+
 /* Parseval sums in FP64: out[0] = sum f^2 / (nx ny nz) over the real field (batch
  * member 0), out[1] = sum w(kz) |F|^2 over its half spectrum.  Synchronises stream. */
 tk_status fft3d_parseval(tk_fft3d_t plan, const void *real, const void *cplx, double out[2],

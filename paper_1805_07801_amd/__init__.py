@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libtk.so")
 TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ESTATE = 0, -1, -2, -3, -4, -5
 TK_F32, TK_F64 = 0, 1
 TK_FFT_TIMING, TK_FFT_NO_TUNE, TK_FFT_C2R_Y_FIRST, TK_FFT_C2R_OVERWRITE = 0x1, 0x2, 0x4, 0x8
+TK_SCRATCH_BYTES = 80 << 20
 
 _lib = None
 
@@ -54,6 +55,7 @@ def _declare(L):
         "fft3d_set_workspace": ([vp, vp], i),
         "fft3d_r2c": ([vp, vp, vp, vp], i),
         "fft3d_c2r": ([vp, vp, vp, vp], i),
+        "fft3d_c2r_noalloc": ([vp, vp, vp, vp], i),
         "fft3d_parseval": ([vp, vp, vp, P(d), vp], i),
         "fft3d_pass_times": ([vp, P(ctypes.c_float)], i),
         "fft3d_describe": ([vp, i, ctypes.c_char_p, i], i),
@@ -265,6 +267,14 @@ class FFT3D:
         out = self.empty_real() if out is None else out
         self._check_real(out)
         check(lib().fft3d_c2r(self.h, _ptr(cplx), _ptr(out), _stream(stream)))
+        return out
+
+    def c2r_noalloc(self, cplx, out, stream=None):
+        """c2r through the allocation-free entry point (static device scratch as the
+        workspace); `out` must be given."""
+        self._check_cplx(cplx)
+        self._check_real(out)
+        check(lib().fft3d_c2r_noalloc(self.h, _ptr(cplx), _ptr(out), _stream(stream)))
         return out
 
     def parseval(self, real, cplx, stream=None):

@@ -6,6 +6,7 @@
 // is never permuted (Appendix A), the Y and X passes read strided columns.
 // Inverse: X c2c^-1 cplx_in -> workspace ; Y c2c^-1 in place ; Z c2r workspace -> real_out.
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "fft_api.hpp"
@@ -274,27 +275,46 @@ extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out
     return TK_OK;
 }
 
+// The inverse passes.  ws == nullptr: in place on the input (TK_FFT_C2R_OVERWRITE);
+// else the X (or Y) inverse writes ws out of place and the input is preserved.
+static tk_status c2r_run(tk_fft3d_s *p, const void *cplx_in, void *ws, void *real_out, hipStream_t s) {
+    const FftAxes &ax = p->ax;
+    hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
+    const bool y_first = ws && (p->flags & TK_FFT_C2R_Y_FIRST);
+    if (!ws) {
+        // in place on the input: X backwards (the forward X pass wrote those columns last),
+        // Y, then Z backwards into the output
+        void *w = const_cast<void *>(cplx_in);
+        TK_TRY(fft_x_pass(ax, w, w, p->batch, 1, 1.0, s, 1));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_y_pass(ax, w, w, p->batch, 1, s));
+        ws = w;
+    } else if (y_first) {
+        // the X and Y inverses commute: the one out-of-place pass is then the Y pass
+        TK_TRY(fft_y_pass(ax, cplx_in, ws, p->batch, 1, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_x_pass(ax, ws, ws, p->batch, 1, 1.0, s));
+    } else {
+        // X backwards over the columns the forward X pass wrote last, then Z backwards over
+        // the x planes the Y pass wrote last
+        TK_TRY(fft_x_pass(ax, cplx_in, ws, p->batch, 1, 1.0, s, 1));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(fft_y_pass(ax, ws, ws, p->batch, 1, s));
+    }
+    if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
+    TK_TRY(fft_z_c2r(ax, ws, real_out, p->batch, s, y_first ? 0 : 1));
+    if (ev) {
+        TK_HIP_CHECK(hipEventRecord(ev[7], s));
+        p->nc2r++;
+    }
+    return TK_OK;
+}
+
 extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out, void *stream) {
     if (!p || !cplx_in || !real_out) return fail(TK_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    const FftAxes &ax0 = p->ax;
-    if (p->flags & TK_FFT_C2R_OVERWRITE) {
-        // in place on the input: X backwards (the forward X pass wrote those columns last),
-        // Y, then Z backwards into the output
-        hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
-        void *w = const_cast<void *>(cplx_in);
-        if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
-        TK_TRY(fft_x_pass(ax0, w, w, p->batch, 1, 1.0, s, 1));
-        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
-        TK_TRY(fft_y_pass(ax0, w, w, p->batch, 1, s));
-        if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
-        TK_TRY(fft_z_c2r(ax0, w, real_out, p->batch, s, 1));
-        if (ev) {
-            TK_HIP_CHECK(hipEventRecord(ev[7], s));
-            p->nc2r++;
-        }
-        return TK_OK;
-    }
+    if (p->flags & TK_FFT_C2R_OVERWRITE) return c2r_run(p, cplx_in, nullptr, real_out, s);
     if (!p->ws) {
         if (hipMalloc(&p->ws, cplx_bytes(p)) != hipSuccess) {
             p->ws = nullptr;
@@ -302,28 +322,46 @@ extern "C" tk_status fft3d_c2r(tk_fft3d_t p, const void *cplx_in, void *real_out
         }
         p->ws_owned = true;
     }
-    const FftAxes &ax = p->ax;
-    hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
-    if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
-    if (p->flags & TK_FFT_C2R_Y_FIRST) {
-        // the X and Y inverses commute: the one out-of-place pass is then the Y pass
-        TK_TRY(fft_y_pass(ax, cplx_in, p->ws, p->batch, 1, s));
-        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
-        TK_TRY(fft_x_pass(ax, p->ws, p->ws, p->batch, 1, 1.0, s));
-    } else {
-        // X backwards over the columns the forward X pass wrote last, then Z backwards over
-        // the x planes the Y pass wrote last
-        TK_TRY(fft_x_pass(ax, cplx_in, p->ws, p->batch, 1, 1.0, s, 1));
-        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
-        TK_TRY(fft_y_pass(ax, p->ws, p->ws, p->batch, 1, s));
+    return c2r_run(p, cplx_in, p->ws, real_out, s);
+}
+
+// Workspace of fft3d_c2r_noalloc: a file-scope device array that each device holds from
+// the moment this code object is loaded on it until the process ends.  In host code its
+// name is only a host-side stand-in: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[TK_SCRATCH_BYTES];
+
+static const int kMaxDevices = 64;
+
+static tk_status scratch_address(void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    TK_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TK_EUNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TK_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        addr[dev] = ptr;
     }
-    if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
-    TK_TRY(fft_z_c2r(ax, p->ws, real_out, p->batch, s, (p->flags & TK_FFT_C2R_Y_FIRST) ? 0 : 1));
-    if (ev) {
-        TK_HIP_CHECK(hipEventRecord(ev[7], s));
-        p->nc2r++;
-    }
+    *out = addr[dev];
     return TK_OK;
+}
+
+extern "C" tk_status fft3d_c2r_noalloc(tk_fft3d_t p, const void *cplx_in, void *real_out, void *stream) {
+    if (!p || !cplx_in || !real_out) return fail(TK_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->flags & TK_FFT_C2R_OVERWRITE) return c2r_run(p, cplx_in, nullptr, real_out, s);
+    const size_t need = cplx_bytes(p);
+    if (need > TK_SCRATCH_BYTES)
+        return fail(TK_EINVAL, "fft3d_c2r_noalloc: workspace of %zu bytes exceeds the static scratch of %zu bytes",
+                    need, (size_t)TK_SCRATCH_BYTES);
+    void *ws = nullptr;
+    TK_TRY(scratch_address(&ws));
+    return c2r_run(p, cplx_in, ws, real_out, s);
 }
 
 extern "C" tk_status fft3d_pass_times(tk_fft3d_t p, float t[6]) {
