@@ -95,3 +95,19 @@ def rel_l2(a, b, n=None):
         num = np.sum(np.abs(a - b) ** 2)
         den = np.sum(np.abs(b) ** 2)
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+
+
+def shell_rel_l2(a, b, n, shells):
+    """Relative L2 error per shell, sqrt(sum_s w |a - b|^2 / sum_s w |b|^2), for each
+    shell s in ``shells`` ([...][n][n][n/2+1] half-spectrum arrays, summed over the
+    leading axes)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    s = shell_index(n)
+    w = fft.hermitian_weight(n)
+    lead = tuple(range(a.ndim - 3))
+    num = np.broadcast_to(w * np.sum(np.abs(a - b) ** 2, axis=lead), s.shape)
+    den = np.broadcast_to(w * np.sum(np.abs(b) ** 2, axis=lead), s.shape)
+    sn = np.bincount(s.ravel(), weights=num.ravel())
+    sd = np.bincount(s.ravel(), weights=den.ravel())
+    return np.array([np.sqrt(sn[k] / sd[k]) if sd[k] > 0 else np.sqrt(sn[k]) for k in shells])

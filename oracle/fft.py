@@ -123,6 +123,27 @@ def dft_at(f, ks):
     return np.array(out) / (nx * ny * nz)
 
 
+def dft_planes(f, kzs, chunk=64):
+    """The forward transform on complete kz-planes: F[:, :, kz] for each kz in kzs, from
+    the definition along z (a direct sum over the nz samples) followed by the 1D
+    transform of every y-line and then every x-line of each plane, with the 1/N^3
+    factor.  Cost O(N^3) per plane: checks complete planes of grids too large for the
+    full oracle transform."""
+    f = np.asarray(f)
+    nx, ny, nz = f.shape
+    kzs = [int(k) for k in kzs]
+    ez = np.exp(-2j * np.pi * np.outer(np.arange(nz), kzs) / nz)            # [nz][K]
+    g = np.empty((nx, ny, len(kzs)), dtype=np.complex128)
+    for a in range(0, nx, chunk):
+        b = min(nx, a + chunk)
+        g[a:b] = (f[a:b].reshape(-1, nz).astype(np.float64) @ ez).reshape(b - a, ny, len(kzs))
+    out = np.empty((len(kzs), nx, ny), dtype=np.complex128)
+    for i in range(len(kzs)):
+        p = np.stack([fft1d(g[a, :, i], -1) for a in range(nx)])            # Y transform of each x row
+        out[i] = np.stack([fft1d(p[:, b], -1) for b in range(ny)], axis=1)  # X transform of each column
+    return out / (nx * ny * nz)
+
+
 def idft_at(F, nz, xs):
     """The inverse transform's definition at selected grid points (ix, iy, iz):
     f(x) = sum_{kz} w(kz) Re[sum_{kx,ky} F(k) exp(i k.x)]."""
@@ -175,6 +196,42 @@ def _r2r_matrix(n, basis, inverse):
 
 def _apply_axis(a, M, axis):
     return np.moveaxis(np.tensordot(M, np.moveaxis(a, axis, 0), axes=(1, 0)), 0, axis)
+
+
+def dft_x_lines_basis(f, bx, cols):
+    """The forward transform with basis bx along x (Fourier along y and z) on complete
+    x-lines: F[:, ky, kz] for each (ky index, kz) in cols, from direct sums over y and z
+    (1/ny, 1/nz) followed by the x basis (fft1d / nx, or the sine / cosine sums)."""
+    f = np.asarray(f)
+    nx, ny, nz = f.shape
+    out = []
+    for (b, c) in cols:
+        ez = np.exp(-2j * np.pi * c * np.arange(nz) / nz) / nz
+        ey = np.exp(-2j * np.pi * b * np.arange(ny) / ny) / ny
+        p = np.array([ey @ (f[a].astype(np.float64) @ ez) for a in range(nx)])   # [nx]
+        out.append(fft1d(p, -1) / nx if bx == FOURIER else _r2r_matrix(nx, bx, False) @ p)
+    return np.array(out)
+
+
+def idft_x_lines_basis(F, nz, bx, points):
+    """The inverse transform with basis bx along x (Fourier along y and z) on complete
+    x-lines: f[:, iy, iz] for each (iy, iz) in points, f = sum_kz w(kz) Re[sum_ky
+    e^{i ky y} e^{i kz z} (x basis sum over kx)]."""
+    F = np.asarray(F)
+    nx, ny, nzh = F.shape
+    w = np.full(nzh, 2.0)
+    w[0] = 1.0
+    w[nz // 2] = 1.0
+    out = []
+    for (b, c) in points:
+        ey = np.exp(2j * np.pi * b * np.arange(ny) / ny)
+        ez = w * np.exp(2j * np.pi * c * np.arange(nzh) / nz)
+        h = np.array([ey @ (F[a].astype(np.complex128) @ ez) for a in range(nx)])   # [nkx]
+        if bx == FOURIER:
+            out.append(np.real(fft1d(h, +1)))
+        else:  # a real basis: the real part may be taken before the x sum
+            out.append(_r2r_matrix(nx, bx, True) @ np.real(h))
+    return np.array(out)
 
 
 def rfft3_basis(f, bx=FOURIER, by=FOURIER):

@@ -29,3 +29,12 @@ def tk():
     import paper_1805_07801_amd as tkmod
     tkmod.load()
     return tkmod
+
+
+@pytest.fixture(scope="session")
+def band512():
+    """The 512^3 band-filling solenoidal field (every kept mode O(1), unit energy, FP64,
+    from the seed-2 noise), built once by the oracle and shared by the full-size tests."""
+    import synth
+    from oracle import init as oinit
+    return oinit.band_filling(synth.gaussian_field((3, 512, 512, 512), 2))

@@ -26,6 +26,19 @@ def rand_state(n, seed):
     return oinit.random_solenoidal(synth.gaussian_field((3, n, n, n), seed))
 
 
+def band_state(n, seed):
+    """Every kept mode O(1): parity measured on this field sees the whole 2/3 band (the
+    decaying-turbulence field holds almost no energy beyond shell 20)."""
+    return oinit.band_filling(synth.gaussian_field((3, n, n, n), seed))
+
+
+def assert_shells(got, ref, n, tol):
+    """Relative L2 error of every shell 1..K (K = (n-1)//3, the 2/3 cutoff) within tol."""
+    K = (n - 1) // 3
+    e = diag.shell_rel_l2(got, ref, n, range(1, K + 1))
+    assert np.max(e) <= tol, (int(np.argmax(e)) + 1, float(np.max(e)))
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128])
 def test_rhs_vs_oracle(tk, n, dt):
@@ -45,7 +58,7 @@ def test_rhs_every_solver_variant_vs_oracle(tk, n):
     autotuner's choices) reproduces the oracle's right-hand side; the masked modes stay
     exactly zero."""
     import torch
-    u = rand_state(n, seed=n + 1)
+    u = band_state(n, seed=n + 1)
     ref = ons.rhs(u)
     ud = to_gpu(u, "f32")
     try:
@@ -58,6 +71,7 @@ def test_rhs_every_solver_variant_vs_oracle(tk, n):
                 got = s.rhs(ud).cpu().numpy()
                 s.close()
                 assert diag.rel_l2(got, ref, n) <= 1e-5, (p, a, E)
+                assert_shells(got, ref, n, 1e-4)
                 assert np.max(np.abs(got * ~ons.dealias_mask(n))) == 0, (p, a, E)
             tk.tune_set(n, torch.float32, p, 0, 0)
     finally:
@@ -84,7 +98,7 @@ def test_taylor_green_32_ten_steps(tk, dt):
 @pytest.mark.parametrize("scheme", ["rk2", "rk4"])
 @pytest.mark.parametrize("n,dt", [(24, "f64"), (48, "f32"), (96, "f32"), (128, "f32"), (64, "f64")])
 def test_one_step_vs_oracle(tk, n, dt, scheme):
-    u = rand_state(n, seed=100 + n)
+    u = band_state(n, seed=100 + n)
     nu, h = 2e-3, 0.004
     stepper = ons.ifrk2_step if scheme == "rk2" else ons.ifrk4_step
     res = stepper(u, nu, h)
@@ -92,8 +106,10 @@ def test_one_step_vs_oracle(tk, n, dt, scheme):
     s = tk.NS(n, dtype=tdt(dt), nu=nu, scheme=scheme)
     ud = to_gpu(u, dt)
     s.step(ud, h, 1)
-    err = diag.rel_l2(ud.cpu().numpy(), ref, n)
+    got = ud.cpu().numpy()
+    err = diag.rel_l2(got, ref, n)
     assert err <= (1e-12 if dt == "f64" else 1e-4), err
+    assert_shells(got, ref, n, 1e-11 if dt == "f64" else 1e-4)
 
 
 @pytest.mark.parametrize("scheme", ["rk2", "rk4"])
@@ -197,8 +213,10 @@ def test_inviscid_energy_and_divergence(tk):
     assert d["max_div"] <= 1e-5
 
 
-def test_rhs_512_vs_oracle(tk):
-    """512^3 FP32: one right-hand side of the decaying-turbulence initial field."""
+def test_rhs_512_vs_oracle(tk, band512):
+    """512^3 FP32: the decaying-turbulence initial field against the oracle's, then one
+    right-hand side of a band-filling field (every kept mode O(1)), globally and shell by
+    shell up to the cutoff K = 170."""
     import torch
     n = 512
     noise = synth.gaussian_field((3, n, n, n), 1)
@@ -207,9 +225,12 @@ def test_rhs_512_vs_oracle(tk):
     u = oinit.random_solenoidal(noise)
     del noise
     assert diag.rel_l2(ud.cpu().numpy(), u, n) <= 1e-5
-    got = s.rhs(ud).cpu().numpy()
-    ref = ons.rhs(u)
+    del u, ud
+    got = s.rhs(to_gpu(band512, "f32")).cpu().numpy()
+    ref = ons.rhs(band512)
     assert diag.rel_l2(got, ref, n) <= 1e-5
+    assert_shells(got, ref, n, 1e-4)
+    assert np.max(np.abs(got * ~ons.dealias_mask(n))) == 0
 
 
 def test_pass_times_leave_the_state_alone(tk):

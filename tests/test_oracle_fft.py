@@ -153,3 +153,27 @@ def test_sampled_definitions_match_full_transform():
     assert np.max(np.abs(got - np.array([F[k] for k in ks]))) <= 1e-15
     xs = [(0, 0, 0), (5, 7, 3), (23, 11, 15)]
     assert np.max(np.abs(fft.idft_at(F, 16, xs) - np.array([f[x] for x in xs]))) <= 1e-13
+
+
+def test_plane_and_line_evaluators_match_the_full_transform():
+    """The large-grid evaluators (complete kz-planes; complete x-lines in a Fourier, sine
+    or cosine x basis, forward and inverse) agree with the full 3D oracle transforms."""
+    from oracle import fft as offt
+    rng = np.random.default_rng(17)
+    f = rng.standard_normal((24, 12, 16))
+    F = offt.rfft3(f)
+    P = offt.dft_planes(f, [0, 3, 8], chunk=5)
+    for i, kz in enumerate([0, 3, 8]):
+        assert np.max(np.abs(P[i] - F[:, :, kz])) <= 1e-15
+    cols = [(0, 0), (5, 3), (11, 8)]
+    pts = [(0, 0), (7, 13), (11, 15)]
+    G = rng.standard_normal(F.shape) + 1j * rng.standard_normal(F.shape)
+    for bx in (offt.FOURIER, offt.SINE, offt.COSINE):
+        Fb = offt.rfft3_basis(f, bx, offt.FOURIER)
+        L = offt.dft_x_lines_basis(f, bx, cols)
+        for i, (b, c) in enumerate(cols):
+            assert np.max(np.abs(L[i] - Fb[:, b, c])) <= 1e-15
+        g = offt.irfft3_basis(G, 16, bx, offt.FOURIER)
+        Li = offt.idft_x_lines_basis(G, 16, bx, pts)
+        for i, (b, c) in enumerate(pts):
+            assert np.max(np.abs(Li[i] - g[:, b, c])) <= 1e-14 * np.max(np.abs(g))
