@@ -283,3 +283,27 @@ def irfft3_basis(F, nz, bx=FOURIER, by=FOURIER):
             line[nz // 2 + 1:] = np.conj(g[a, b, 1:nz // 2][::-1])
             out[a, b] = fft1d(line, +1).real
     return out
+
+
+def rfft3_sss(f, bx, by, bz):
+    """Forward 3D transform with a sine or cosine basis on every axis (the paper's SSS
+    family, e.g. cos x, cos y, sin z for u_z): real [nx][ny][nz] -> real coefficients
+    [nx][ny][nz], each axis by its own definition (1/N per axis), z first, then y, then x."""
+    if FOURIER in (bx, by, bz):
+        raise ValueError("rfft3_sss: every axis needs the sine or cosine basis")
+    f = np.asarray(f, dtype=np.float64)
+    nx, ny, nz = f.shape
+    out = _apply_axis(f, _r2r_matrix(nz, bz, False), 2)
+    out = _apply_axis(out, _r2r_matrix(ny, by, False), 1)
+    return _apply_axis(out, _r2r_matrix(nx, bx, False), 0)
+
+
+def irfft3_sss(F, bx, by, bz):
+    """Inverse of rfft3_sss: the basis sums along x, then y, then z."""
+    if FOURIER in (bx, by, bz):
+        raise ValueError("irfft3_sss: every axis needs the sine or cosine basis")
+    F = np.asarray(F, dtype=np.float64)
+    nx, ny, nz = F.shape
+    g = _apply_axis(F, _r2r_matrix(nx, bx, True), 0)
+    g = _apply_axis(g, _r2r_matrix(ny, by, True), 1)
+    return _apply_axis(g, _r2r_matrix(nz, bz, True), 2)

@@ -49,3 +49,32 @@ def test_single_modes():
     exp = np.zeros_like(G)
     exp[1, 0, 0] = 0.5
     assert np.max(np.abs(G - exp)) <= 1e-15
+
+
+@pytest.mark.parametrize("b", [(2, 2, 1), (1, 2, 2), (1, 1, 1), (2, 2, 2), (2, 1, 1)])
+def test_sss_matches_scipy_and_round_trips(b):
+    """SSS family (a sine or cosine basis on every axis): scipy's independent multi-axis
+    DCT-II / DST-II (each axis its own type), the round trip, and a single mode: the
+    u_z basis function 8 cos(kx x) cos(ky y) sin(kz z) of the paper's Section "Fast Fourier
+    Transform" has the one coefficient 1 (sin 0 is the zero function, so a sine k starts
+    at 1, stored at index k - 1)."""
+    bx, by, bz = b
+    rng = np.random.default_rng(sum(b))
+    f = rng.standard_normal((8, 12, 10))
+    F = fft.rfft3_sss(f, bx, by, bz)
+    ref = f.copy()
+    for ax, bb in zip(range(3), b):
+        n = f.shape[ax]
+        ref = (sf.dct(ref, type=2, axis=ax) if bb == fft.COSINE else sf.dst(ref, type=2, axis=ax)) / (2 * n)
+    assert np.max(np.abs(F - ref)) <= 1e-15
+    assert np.max(np.abs(fft.irfft3_sss(F, bx, by, bz) - f)) <= 1e-13
+    nx, ny, nz = 8, 12, 10
+    grid = [np.pi * (np.arange(n) + 0.5) / n for n in (nx, ny, nz)]
+    kx, ky, kz = 3, 2, 4
+    g = 8 * np.cos(kx * grid[0])[:, None, None] * np.cos(ky * grid[1])[None, :, None] * np.sin(kz * grid[2])[None, None, :]
+    G = fft.rfft3_sss(g, fft.COSINE, fft.COSINE, fft.SINE)
+    exp = np.zeros_like(G)
+    exp[kx, ky, kz - 1] = 1.0
+    assert np.max(np.abs(G - exp)) <= 1e-14
+    with pytest.raises(ValueError):
+        fft.rfft3_sss(f, fft.FOURIER, 1, 1)
