@@ -94,6 +94,17 @@ tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz, int batch,
 tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt, int basis_x,
                                   int basis_y, unsigned flags);
 
+/* As fft3d_plan_create_basis with a basis along z too.  basis_z = TK_FOURIER is
+ * fft3d_plan_create_basis.  A sine or cosine z basis (the SSS family of the paper's
+ * Section "Fast Fourier Transform", e.g. cos x cos y sin z for u_z of free-slip walls)
+ * needs sine or cosine x and y bases (else TK_EUNSUPPORTED): every axis then takes its
+ * sine / cosine transform as above (z on the grid z_j = pi (j + 1/2) / nz too, 1/N per axis
+ * forward), and the spectral data are REAL, [batch][nx][ny][nz] of dtype dt, coefficient
+ * (kx, ky, kz) at [kx][ky][kz] (sine k at index k - 1), wherever the calls below say
+ * "cplx".  fft3d_parseval does not apply to such plans (TK_EUNSUPPORTED). */
+tk_status fft3d_plan_create_basis3(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt, int basis_x,
+                                   int basis_y, int basis_z, unsigned flags);
+
 /* Bytes of device workspace fft3d_c2r needs (one spectral field per batch member; none
  * with TK_FFT_C2R_OVERWRITE). */
 tk_status fft3d_workspace_size(tk_fft3d_t plan, size_t *bytes);

@@ -307,3 +307,22 @@ def irfft3_sss(F, bx, by, bz):
     g = _apply_axis(F, _r2r_matrix(nx, bx, True), 0)
     g = _apply_axis(g, _r2r_matrix(ny, by, True), 1)
     return _apply_axis(g, _r2r_matrix(nz, bz, True), 2)
+
+
+def sss_lines(a, bx, by, bz, axis, pts, inverse=False):
+    """Complete lines along `axis` (0 = x, 2 = z) of the SSS transform of a (forward) or
+    of its inverse, at the points pts of the two other axes (index pairs, in axis order):
+    the basis sums along those two axes at the given indices, then the whole line along
+    `axis`.  Cost O(N^3) per line: checks grids too large for rfft3_sss."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape
+    M = [_r2r_matrix(n[0], bx, inverse), _r2r_matrix(n[1], by, inverse), _r2r_matrix(n[2], bz, inverse)]
+    out = []
+    for (p, q) in pts:
+        if axis == 2:
+            line = M[1][q] @ (M[0][p] @ a.reshape(n[0], -1)).reshape(n[1], n[2])
+            out.append(M[2] @ line)
+        else:
+            line = (a.reshape(-1, n[2]) @ M[2][q]).reshape(n[0], n[1]) @ M[1][p]
+            out.append(M[0] @ line)
+    return np.array(out)

@@ -51,6 +51,7 @@ def _declare(L):
         "tk_sum_squares": ([vp, ctypes.c_long, i, P(d), vp], i),
         "fft3d_plan_create": ([P(vp), i, i, i, i, i, u], i),
         "fft3d_plan_create_basis": ([P(vp), i, i, i, i, i, i, i, u], i),
+        "fft3d_plan_create_basis3": ([P(vp), i, i, i, i, i, i, i, i, u], i),
         "fft3d_workspace_size": ([vp, P(sz)], i),
         "fft3d_set_workspace": ([vp, vp], i),
         "fft3d_r2c": ([vp, vp, vp, vp], i),
@@ -216,8 +217,10 @@ def tune_load(path):
 class FFT3D:
     """Plan for batched 3D r2c / c2r transforms of [batch][nx][ny][nz] real fields."""
 
-    def __init__(self, nx, ny=None, nz=None, batch=1, dtype=None, flags=0, basis_x=0, basis_y=0):
-        """basis_x / basis_y: 0 Fourier, 1 sine, 2 cosine (z is Fourier)."""
+    def __init__(self, nx, ny=None, nz=None, batch=1, dtype=None, flags=0, basis_x=0, basis_y=0, basis_z=0):
+        """basis_x / basis_y / basis_z: 0 Fourier, 1 sine, 2 cosine.  A sine / cosine z basis
+        (the SSS family) needs sine / cosine x and y bases; its spectral data are real
+        [batch][nx][ny][nz]."""
         import torch
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
@@ -225,14 +228,25 @@ class FFT3D:
         self.shape = (nx, ny, nz)
         self.batch = batch
         self.dtype = dtype
-        self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
+        self.sss = basis_z != 0
+        if self.sss:
+            self.cdtype = dtype
+        else:
+            self.cdtype = torch.complex64 if _dtype_code(dtype) == TK_F32 else torch.complex128
         h = ctypes.c_void_p()
-        if basis_x or basis_y:
+        if basis_z:
+            check(lib().fft3d_plan_create_basis3(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), basis_x,
+                                                 basis_y, basis_z, flags))
+        elif basis_x or basis_y:
             check(lib().fft3d_plan_create_basis(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), basis_x,
                                                 basis_y, flags))
         else:
             check(lib().fft3d_plan_create(ctypes.byref(h), nx, ny, nz, batch, _dtype_code(dtype), flags))
         self.h = h
+
+    def spectral_shape(self):
+        nx, ny, nz = self.shape
+        return (self.batch, nx, ny, nz) if self.sss else (self.batch, nx, ny, nz // 2 + 1)
 
     def _check_real(self, t):
         nx, ny, nz = self.shape
@@ -241,15 +255,15 @@ class FFT3D:
                           % (self.dtype, self.batch * nx * ny * nz))
 
     def _check_cplx(self, t):
-        nx, ny, nz = self.shape
-        n = self.batch * nx * ny * (nz // 2 + 1)
+        n = 1
+        for d in self.spectral_shape():
+            n *= d
         if t.dtype != self.cdtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
-            raise TkError(TK_EINVAL, "complex tensor must be contiguous %s on GPU with %d elements" % (self.cdtype, n))
+            raise TkError(TK_EINVAL, "spectral tensor must be contiguous %s on GPU with %d elements" % (self.cdtype, n))
 
     def empty_cplx(self):
         import torch
-        nx, ny, nz = self.shape
-        return torch.empty((self.batch, nx, ny, nz // 2 + 1), dtype=self.cdtype, device="cuda")
+        return torch.empty(self.spectral_shape(), dtype=self.cdtype, device="cuda")
 
     def empty_real(self):
         import torch

@@ -98,10 +98,14 @@ tk_status fft_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields
     return strided_pass(ax.kx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, inv, scale, s, rev);
 }
 
-tk_status axes_set_basis(FftAxes *ax, int bx, int by) {
-    if (bx < 0 || bx > 2 || by < 0 || by > 2) return fail(TK_EINVAL, "basis must be 0 (Fourier), 1 (sine), 2 (cosine)");
+tk_status axes_set_basis(FftAxes *ax, int bx, int by, int bz) {
+    if (bx < 0 || bx > 2 || by < 0 || by > 2 || bz < 0 || bz > 2)
+        return fail(TK_EINVAL, "basis must be 0 (Fourier), 1 (sine), 2 (cosine)");
+    if (bz != 0 && (bx == 0 || by == 0))
+        return fail(TK_EUNSUPPORTED, "a sine / cosine z basis needs sine / cosine x and y bases (SSS family)");
     ax->bx = bx;
     ax->by = by;
+    ax->bz = bz;
     tk_status st;
     for (int axis = 0; axis < 2; ++axis) {
         const int b = axis == 0 ? bx : by;
@@ -121,7 +125,33 @@ tk_status axes_set_basis(FftAxes *ax, int bx, int by) {
             ax->twqy = tq;
         }
     }
+    if (bz) {
+        for (const auto &q : z_r2r_kernels())
+            if (q.L == ax->nz && q.dt == ax->dt) ax->rz = &q;
+        if (!ax->rz) return fail(TK_EUNSUPPORTED, "no z sine/cosine kernel for length %d", ax->nz);
+        ax->twqz = twiddle_table(4 * ax->nz, ax->dt, &st);
+        if (!ax->twqz) return st;
+    }
     return TK_OK;
+}
+
+// SSS family: kinds 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III (as the strided sine/cosine pass)
+tk_status sss_z_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s) {
+    ZR2RArgs a{src, dst, nfields * ax.nx * ax.ny / 2, ax.twz, ax.twqz, (inv ? 2 : 0) + (ax.bz == 1 ? 1 : 0), 1.0};
+    ax.rz->fn(a, s);
+    return launch_check("z sine/cosine pass");
+}
+
+tk_status sss_y_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, hipStream_t s) {
+    const long nzc = ax.nz / 2;  // complex pairs along z
+    return r2r_pass(ax.ry, ax.by, src, dst, nfields * ax.nx * nzc, nzc, (long)ax.ny * nzc, nzc, ax.twy, ax.twqy,
+                    inv, 1.0, s);
+}
+
+tk_status sss_x_pass(const FftAxes &ax, const void *src, void *dst, long nfields, int inv, double scale,
+                     hipStream_t s) {
+    const long cb = (long)ax.ny * (ax.nz / 2);
+    return r2r_pass(ax.rx, ax.bx, src, dst, nfields * cb, cb, (long)ax.nx * cb, cb, ax.twx, ax.twqx, inv, scale, s);
 }
 
 tk_status fft_z_r2c(const FftAxes &ax, const void *src, void *dst, long nfields, double scale, hipStream_t s,
@@ -188,8 +218,10 @@ struct tk_fft3d_s {
     int nr2c, nc2r;
 };
 
+// Bytes of the spectral data: the half spectrum, or for the SSS family a real field.
 static size_t cplx_bytes(const tk_fft3d_s *p) {
-    size_t esz = p->ax.dt == TK_F32 ? 8 : 16;
+    const size_t esz = p->ax.dt == TK_F32 ? 8 : 16;
+    if (p->ax.bz) return esz / 2 * (size_t)p->batch * p->ax.nx * p->ax.ny * p->ax.nz;
     return esz * (size_t)p->batch * p->ax.nx * p->ax.ny * (p->ax.nz / 2 + 1);
 }
 
@@ -231,8 +263,13 @@ extern "C" tk_status fft3d_plan_create(tk_fft3d_t *plan, int nx, int ny, int nz,
 
 extern "C" tk_status fft3d_plan_create_basis(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
                                              int basis_x, int basis_y, unsigned flags) {
+    return fft3d_plan_create_basis3(plan, nx, ny, nz, batch, dt, basis_x, basis_y, TK_FOURIER, flags);
+}
+
+extern "C" tk_status fft3d_plan_create_basis3(tk_fft3d_t *plan, int nx, int ny, int nz, int batch, tk_dtype dt,
+                                              int basis_x, int basis_y, int basis_z, unsigned flags) {
     TK_TRY(fft3d_plan_create(plan, nx, ny, nz, batch, dt, flags));
-    tk_status st = axes_set_basis(&(*plan)->ax, basis_x, basis_y);
+    tk_status st = axes_set_basis(&(*plan)->ax, basis_x, basis_y, basis_z);
     if (st != TK_OK) {
         fft3d_plan_destroy(*plan);
         *plan = nullptr;
@@ -261,6 +298,18 @@ extern "C" tk_status fft3d_r2c(tk_fft3d_t p, const void *real_in, void *cplx_out
     const double scale = 1.0 / ((double)ax.nx * ax.ny * ax.nz);
     hipEvent_t *ev = p->timing ? &p->ev[(p->nr2c % NSET) * 8] : nullptr;
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[0], s));
+    if (ax.bz) {
+        TK_TRY(sss_z_pass(ax, real_in, cplx_out, p->batch, 0, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[1], s));
+        TK_TRY(sss_y_pass(ax, cplx_out, cplx_out, p->batch, 0, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[2], s));
+        TK_TRY(sss_x_pass(ax, cplx_out, cplx_out, p->batch, 0, scale, s));
+        if (ev) {
+            TK_HIP_CHECK(hipEventRecord(ev[3], s));
+            p->nr2c++;
+        }
+        return TK_OK;
+    }
     // sweep directions: each pass starts where the previous one ended (its last writes are
     // still in the memory-side cache) when the two visit the data in the same order
     TK_TRY(fft_z_r2c(ax, real_in, cplx_out, p->batch, 1.0, s));
@@ -281,6 +330,20 @@ static tk_status c2r_run(tk_fft3d_s *p, const void *cplx_in, void *ws, void *rea
     const FftAxes &ax = p->ax;
     hipEvent_t *ev = p->timing ? &p->ev[(p->nc2r % NSET) * 8] : nullptr;
     if (ev) TK_HIP_CHECK(hipEventRecord(ev[4], s));
+    if (ax.bz) {
+        // SSS family: X, then Y, in place on ws (or on the input), then Z into the output
+        void *w = ws ? ws : const_cast<void *>(cplx_in);
+        TK_TRY(sss_x_pass(ax, cplx_in, w, p->batch, 1, 1.0, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[5], s));
+        TK_TRY(sss_y_pass(ax, w, w, p->batch, 1, s));
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[6], s));
+        TK_TRY(sss_z_pass(ax, w, real_out, p->batch, 1, s));
+        if (ev) {
+            TK_HIP_CHECK(hipEventRecord(ev[7], s));
+            p->nc2r++;
+        }
+        return TK_OK;
+    }
     const bool y_first = ws && (p->flags & TK_FFT_C2R_Y_FIRST);
     if (!ws) {
         // in place on the input: X backwards (the forward X pass wrote those columns last),
@@ -398,6 +461,7 @@ extern "C" tk_status fft3d_pass_times(tk_fft3d_t p, float t[6]) {
 extern "C" tk_status fft3d_parseval(tk_fft3d_t p, const void *real, const void *cplx, double out[2], void *stream) {
     if (!p || !real || !cplx || !out) return fail(TK_EINVAL, "NULL argument");
     const FftAxes &ax = p->ax;
+    if (ax.bz) return fail(TK_EUNSUPPORTED, "fft3d_parseval: the half-spectrum sums do not apply to the SSS family");
     long npts = (long)ax.nx * ax.ny * ax.nz;
     double a = 0, b = 0;
     TK_TRY(reduce_sumsq_real(real, npts, ax.dt, &a, (hipStream_t)stream));
@@ -411,7 +475,9 @@ extern "C" tk_status fft3d_describe(tk_fft3d_t p, int pass, char *buf, int len) 
     if (!p || !buf || len <= 0) return fail(TK_EINVAL, "bad argument");
     const FftAxes &ax = p->ax;
     int n = 0;
-    if (pass == 0)
+    if (pass == 0 && ax.bz)
+        n = snprintf(buf, len, "z N=%d %s (line pairs)", ax.nz, ax.bz == 1 ? "sine" : "cosine");
+    else if (pass == 0)
         n = snprintf(buf, len, "z N=%d LPW=%d E=%d nt=%d lds=%d", ax.nz, ax.kz->LPW, ax.kz->E, ax.kz->nt, ax.kz->lds);
     else if (pass == 1 || pass == 2) {
         const StridedKernel *k = pass == 1 ? ax.ky : ax.kx;

@@ -84,6 +84,25 @@ struct R2RKernel {
 };
 const std::vector<R2RKernel> &r2r_kernels();
 
+// Sine / cosine transforms along the contiguous z axis of real data: npairs pairs of
+// consecutive real lines of L points (lines 2p and 2p + 1), src -> dst (not in place).
+struct ZR2RArgs {
+    const void *src;
+    void *dst;
+    long npairs;
+    const void *tw;   // W_L^j
+    const void *twq;  // W_{4L}^j, j < L
+    int kind;         // 0 DCT-II, 1 DST-II (forward), 2 DCT-III, 3 DST-III (inverse)
+    double scale;
+};
+using ZR2RFn = void (*)(const ZR2RArgs &, hipStream_t);
+struct ZR2RKernel {
+    int L;
+    tk_dtype dt;
+    ZR2RFn fn;
+};
+const std::vector<ZR2RKernel> &z_r2r_kernels();
+
 #define TK_FOR_EACH_LEN(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 // ---- strided complex pass ----------------------------------------------------------------------

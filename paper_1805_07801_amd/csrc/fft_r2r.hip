@@ -103,6 +103,123 @@ __global__ __launch_bounds__(W *(L / E)) void k_r2r(const V2<T> *src, V2<T> *dst
     }
 }
 
+// Sine / cosine transforms along the contiguous z axis (the SSS family: every axis takes a
+// sine or cosine basis and the data stay real).  Two real lines a, b of L points go through
+// one L-point complex transform as the real and imaginary parts of z = a + i b: every step
+// of the strided kernel above is real-linear, so its formulas hold unchanged with X = X^a
+// + i X^b, and the two lines' coefficients come out as the real and imaginary parts.  The
+// TPL = L / E threads of a line pair are lanes of one wavefront: the mirror value V_{L-k}
+// comes from a lane shuffle and the exchanges need no workgroup barrier.
+template <typename T, int L, int E, int LPW>
+__global__ __launch_bounds__(LPW *(L / E)) void k_z_r2r(const T *__restrict__ src, T *__restrict__ dst, long npairs,
+                                                         const V2<T> *__restrict__ twg, const V2<T> *__restrict__ twqg,
+                                                         int kind, T scale) {
+    using C = V2<T>;
+    constexpr int TPL = L / E;
+    constexpr int NT = LPW * TPL;
+    constexpr int LL = lds_line_len<L>();
+    __shared__ C lds[LPW * LL];
+    __shared__ C tw[L];
+    __shared__ C twq[L];
+    const int tid = threadIdx.x;
+    const int ln = tid / TPL;
+    const int jt = tid % TPL;
+    load_twiddles<T>(tw, twg, L, tid, NT);
+    load_twiddles<T>(twq, twqg, L, tid, NT);  // exp(-i pi k / 2L), k < L
+    const long p = (long)blockIdx.x * LPW + ln;
+    const bool valid = p < npairs;
+    const T *ga = src + (valid ? p : 0) * 2 * L;
+    const T *gb = ga + L;
+    const bool sine = (kind & 1) != 0;
+    C *d = lds + ln * LL;
+    C v[E];
+    __syncthreads();
+    if (kind < 2) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int r = makhoul_row<L>(jt + i * TPL);
+            C x = mk<T>(ga[r], gb[r]);
+            if (sine && (r & 1)) x = mk<T>(-x.x, -x.y);
+            v[i] = x;
+        }
+        line_fft<T, L, E, 1>(v, d, jt, tw);
+        C vm[E];
+        mirror<T, L, E>(v, vm, jt);
+        if (valid) {
+            T *oa = dst + p * 2 * L;
+            T *ob = oa + L;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int k = jt + i * TPL;
+                const C m = cconj(vm[i]);
+                const C a = cscale(cadd(v[i], m), (T)0.5);      // A_k
+                const C dd = csub(v[i], m);                      // 2 i B_k
+                const C b = mk<T>((T)0.5 * dd.y, (T)-0.5 * dd.x);  // B_k
+                const C w = twq[k];
+                const int row = sine ? sine_row<L>(k) : k;
+                oa[row] = (w.x * a.x - w.y * a.y) * scale;
+                ob[row] = (w.x * b.x - w.y * b.y) * scale;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int k = jt + i * TPL;
+            const int row = sine ? sine_row<L>(k) : k;
+            const C x = mk<T>(ga[row], gb[row]);
+            C xm = mk<T>(0, 0);
+            if (k > 0) {
+                const int rm = sine ? sine_row<L>(L - k) : L - k;
+                xm = mk<T>(ga[rm], gb[rm]);
+            }
+            const C t = mk<T>(x.x + xm.y, x.y - xm.x);  // X_k - i X_{L-k}
+            v[i] = cconj(cmul(cconj(twq[k]), t));
+        }
+        line_fft<T, L, E, 1>(v, d, jt, tw);
+        if (valid) {
+            T *oa = dst + p * 2 * L;
+            T *ob = oa + L;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int r = makhoul_row<L>(jt + i * TPL);
+                C y = cconj(v[i]);
+                if (sine && (r & 1)) y = mk<T>(-y.x, -y.y);
+                oa[r] = y.x * scale;
+                ob[r] = y.y * scale;
+            }
+        }
+    }
+}
+
+// Points per thread of the z sine / cosine kernel: a line pair takes at most one wavefront.
+constexpr int zr2r_E(int L) {
+    int E = default_E(L);
+    while (L / E > 64) E *= 2;
+    return E;
+}
+
+template <typename T, int L> void add_z_r2r(std::vector<ZR2RKernel> &v) {
+    constexpr int E = zr2r_E(L);
+    constexpr int TPL = L / E;
+    constexpr int LPW = TPL >= 256 ? 1 : 256 / TPL;
+    v.push_back({L, sizeof(T) == 4 ? TK_F32 : TK_F64, [](const ZR2RArgs &a, hipStream_t s) {
+                     hipLaunchKernelGGL((k_z_r2r<T, L, E, LPW>), dim3(cdiv(a.npairs, LPW)), dim3(LPW * TPL), 0, s,
+                                        (const T *)a.src, (T *)a.dst, a.npairs, (const V2<T> *)a.tw,
+                                        (const V2<T> *)a.twq, a.kind, (T)a.scale);
+                 }});
+}
+
+const std::vector<ZR2RKernel> &z_r2r_kernels() {
+    static std::vector<ZR2RKernel> K = [] {
+        std::vector<ZR2RKernel> v;
+#define TK_R(L) add_z_r2r<float, L>(v); add_z_r2r<double, L>(v);
+        TK_FOR_EACH_LEN(TK_R)
+#undef TK_R
+        return v;
+    }();
+    return K;
+}
+
 template <typename T, int L> void add_r2r(std::vector<R2RKernel> &v) {
     constexpr int E = default_E(L);
     constexpr int W = (512 * E / L) > 0 ? 512 * E / L : 1;

@@ -78,3 +78,20 @@ def test_sss_matches_scipy_and_round_trips(b):
     assert np.max(np.abs(G - exp)) <= 1e-14
     with pytest.raises(ValueError):
         fft.rfft3_sss(f, fft.FOURIER, 1, 1)
+
+
+def test_sss_line_evaluator_matches_full_transform():
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((8, 12, 10))
+    for b in ((2, 2, 1), (1, 2, 2)):
+        F = fft.rfft3_sss(f, *b)
+        g = fft.irfft3_sss(F, *b)
+        Lz = fft.sss_lines(f, *b, axis=2, pts=[(0, 0), (3, 7), (7, 11)])
+        Lx = fft.sss_lines(f, *b, axis=0, pts=[(0, 0), (5, 9), (11, 3)])
+        Iz = fft.sss_lines(F, *b, axis=2, pts=[(2, 4)], inverse=True)
+        for i, (p, q) in enumerate([(0, 0), (3, 7), (7, 11)]):
+            assert np.max(np.abs(Lz[i] - F[p, q, :])) <= 1e-15
+        for i, (p, q) in enumerate([(0, 0), (5, 9), (11, 3)]):
+            assert np.max(np.abs(Lx[i] - F[:, p, q])) <= 1e-15
+        assert np.max(np.abs(Iz[0] - g[2, 4, :])) <= 1e-13
+        assert np.max(np.abs(Iz[0] - f[2, 4, :])) <= 1e-13
