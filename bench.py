@@ -39,9 +39,11 @@ def pair_flops(n):
     return 2 * 5 * n ** 3 * math.log2(n ** 3)
 
 
-def ensemble_rate(tk, torch, steps=10):
-    """The 48-member ensemble (16 x 64^3, 16 x 96^3, 16 x 128^3, CFL 0.5): member-steps/s
-    and grid-point-steps/s, one HIP-graph launch per ensemble step."""
+def ensemble_rate(tk, torch, steps=50):
+    """The 48-member ensemble (16 x 64^3, 16 x 96^3, 16 x 128^3, CFL 0.5): member-steps/s,
+    grid-point-steps/s and the achieved HBM rate over the members' algorithmic bytes per
+    step (two stages of P2, P3, P4 and the fused P5+P1 each), one HIP-graph launch per
+    ensemble step, HIP events on the launch stream."""
     import synth
     sizes = synth.ensemble_sizes()
     ens = tk.Ensemble(sizes, synth.ensemble_viscosities(), cfl=0.5)
@@ -49,14 +51,23 @@ def ensemble_rate(tk, torch, steps=10):
           for i, m in enumerate(sizes)]
     ens.step(st, 0.0, 2)
     torch.cuda.synchronize()
-    t = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
     ens.step(st, 0.0, steps)
+    e1.record()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / steps
+    dt = e0.elapsed_time(e1) * 1e-3 / steps
     pts = sum(m ** 3 for m in sizes)
+    step_bytes = 0
+    for m in sizes:
+        pb = ns_pass_bytes(m)
+        step_bytes += 2 * sum(sum(pb[k]) for k in ("P2", "P3", "P4", "P5+P1"))
     ens.close()
+    gbps = step_bytes / dt / 1e9
     return {"ensemble_steps_per_s": round(1 / dt, 2), "member_steps_per_s": round(len(sizes) / dt, 1),
-            "point_steps_per_s": round(pts / dt, 1)}
+            "point_steps_per_s": round(pts / dt, 1), "ensemble_alg_GB_per_step": round(step_bytes / 1e9, 3),
+            "ensemble_GBps": round(gbps, 1), "ensemble_frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 3)}
 
 
 def les_rate(tk, torch, steps=50):

@@ -180,7 +180,10 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
  * Passes 3, 4, 5 are the solver passes P1 (a = columns), P3 (a = lines per workgroup) and
  * P5 (a = columns) of an L^3 grid (variant 0), pass 6 the solver's Y passes P2 / P4 (a
  * strided tile as for pass 1), pass 7 the time stepper's P5 fused with the next P1 (a =
- * columns); solver handles created afterwards use them.  a <= 0 removes the entry.
+ * columns); solver handles created afterwards use them.  Pass 8 is the tile of the ensemble
+ * kernels of grid size L (FP32 only): a = threads per workgroup, E = default_E(L) (8, or 12
+ * for 3 * 2^a), variant v = persistent grid of 256 << v workgroups (v = 0..6); ensembles
+ * created afterwards use it.  a <= 0 removes the entry.
  * TK_EUNSUPPORTED if no such tile is compiled. */
 tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant);
 
@@ -192,6 +195,15 @@ tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant
  * Allocates 18 spectral fields for the duration of the call.
  * report (may be NULL) receives one text line per variant.  Synchronises. */
 tk_status ns_autotune(int n, tk_dtype dt, int iters, char *report, int report_len);
+
+/* Autotune the ensemble kernels of grid size n (16..128, FP32): an ensemble of `members`
+ * random solenoidal states of that size runs with every compiled thread count (128, 256,
+ * 512 per workgroup) and persistent grid (256 ... 16384 workgroups); a candidate is admitted
+ * only if its states after two fixed steps match the default shape's (256 threads, 1024
+ * workgroups) to relative L2 1e-5, and is timed over `iters` graph-replayed steps; the
+ * fastest admitted one goes into the tile table (pass 8).  Allocates three state copies per
+ * member for the call.  report (may be NULL) receives one line per candidate.  Synchronises. */
+tk_status ns_batch_autotune(int n, int members, int iters, char *report, int report_len);
 
 /* Forget every tuned tile. */
 tk_status fft3d_tune_clear(void);

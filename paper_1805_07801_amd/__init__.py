@@ -65,6 +65,7 @@ def _declare(L):
         "fft3d_tune_set": ([i, i, i, i, i, i], i),
         "fft3d_tune_clear": ([], i),
         "ns_autotune": ([i, i, i, ctypes.c_char_p, i], i),
+        "ns_batch_autotune": ([i, i, i, ctypes.c_char_p, i], i),
         "fft3d_tile_candidates": ([i, i, i, P(i), P(i), P(i), i], i),
         "ns_create": ([P(vp), P(NsConfig)], i),
         "ns_rhs": ([vp, vp, vp, vp], i),
@@ -168,6 +169,15 @@ def ns_autotune(n, iters=5, dtype=None):
     import torch
     buf = ctypes.create_string_buffer(1 << 14)
     check(lib().ns_autotune(n, _dtype_code(dtype or torch.float32), iters, buf, 1 << 14))
+    return buf.value.decode()
+
+
+def ns_batch_autotune(n, members=16, iters=5):
+    """Time every compiled thread count and persistent grid of the ensemble kernels of grid
+    size n and record the fastest that matches the default shape (see ns_batch_autotune).
+    Returns the text report."""
+    buf = ctypes.create_string_buffer(1 << 14)
+    check(lib().ns_batch_autotune(n, members, iters, buf, 1 << 14))
     return buf.value.decode()
 
 

@@ -186,13 +186,15 @@ template <typename V> static int ns_var_index(const V *v, int nv, int a, int E, 
 }
 
 extern "C" tk_status fft3d_tune_set(int L, tk_dtype dt, int pass, int a, int E, int variant) {
-    if (pass < 0 || pass > 7) return fail(TK_EINVAL, "pass must be 0..7");
+    if (pass < 0 || pass > 8) return fail(TK_EINVAL, "pass must be 0..8");
     if (a <= 0) {
         set_tuned_tile(L, dt, pass, {0, 0, 0});
         return TK_OK;
     }
     bool found = false;
-    if ((pass >= 3 && pass <= 5) || pass == 7) {
+    if (pass == 8) {
+        found = dt == TK_F32 && batch_tile_ok(L, a) && E == default_E(L) && variant >= 0 && variant <= 6;
+    } else if ((pass >= 3 && pass <= 5) || pass == 7) {
         const NsKernels *k = ns_kernels_of(L, dt);
         if (k) {
             if (pass == 3) found = ns_var_index(k->p1v, k->np1, a, E, variant) >= 0;
@@ -218,6 +220,19 @@ extern "C" tk_status fft3d_tune_clear(void) {
 
 extern "C" int fft3d_tile_candidates(int L, tk_dtype dt, int pass, int *a, int *E, int *v, int cap) {
     int n = 0;
+    if (pass == 8) {
+        if (dt != TK_F32) return 0;
+        for (int nt : {256, 128, 512}) {
+            if (!batch_tile_ok(L, nt)) continue;
+            for (int gv = 0; gv <= 6; ++gv, ++n)
+                if (n < cap) {
+                    if (a) a[n] = nt;
+                    if (E) E[n] = default_E(L);
+                    if (v) v[n] = gv;
+                }
+        }
+        return n;
+    }
     if ((pass >= 3 && pass <= 5) || pass == 7) {
         const NsKernels *k = ns_kernels_of(L, dt);
         if (!k) return 0;

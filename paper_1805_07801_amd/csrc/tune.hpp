@@ -17,4 +17,7 @@ TileChoice tuned_tile(int L, tk_dtype dt, int pass);
 void set_tuned_tile(int L, tk_dtype dt, int pass, TileChoice c);
 void clear_tuned_tiles();
 
+// Ensemble kernels compiled for grid size n with nt threads per workgroup (pass 8).
+bool batch_tile_ok(int n, int nt);
+
 }  // namespace tk

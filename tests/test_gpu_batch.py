@@ -55,10 +55,51 @@ def test_ensemble_48_cfl(tk):
         assert np.isfinite(d["energy"]) and d["energy"] < e0[i]
         assert d["max_div"] <= 1e-5
         assert 0 < dts[i] < 1.0
-    # member 0 against the oracle for one CFL step from its state
-    n0 = sizes[0]
-    u = states[0].cpu().numpy().astype(np.complex128)
-    h = ons.cfl_dt(u, 0.5)
-    ref = ons.ifrk2_step(u, nus[0], h)[0]
+    # one member of each size class (64^3, 96^3, 128^3) against the oracle for one CFL step
+    # from its state after the five steps
+    picks = [0, 16, 32, 47]
+    us = [states[i].cpu().numpy().astype(np.complex128) for i in picks]
     ens.step(states, 0.0, 1)
-    assert diag.rel_l2(states[0].cpu().numpy(), ref, n0) <= 1e-4
+    dts = ens.last_dt()
+    for i, u in zip(picks, us):
+        n = sizes[i]
+        h = ons.cfl_dt(u, 0.5)
+        assert abs(dts[i] - h) <= 1e-5 * h, (i, n)
+        ref = ons.ifrk2_step(u, nus[i], h)[0]
+        assert diag.rel_l2(states[i].cpu().numpy(), ref, n) <= 1e-4, (i, n)
+
+
+def test_every_ensemble_tile_matches(tk):
+    """Every compiled ensemble shape (threads per workgroup x persistent grid, the
+    autotuner's candidates, tile table pass 8) reproduces the standalone solver's steps and
+    the oracle, for a mixed ensemble of every supported grid size."""
+    import torch
+    sizes = [128, 96, 64, 48, 32, 24, 16]
+    nus = [1e-3 * (1 + i) for i in range(len(sizes))]
+    u0 = [oinit.random_solenoidal(synth.gaussian_field((3, n, n, n), 300 + i)) for i, n in enumerate(sizes)]
+    h, k = 0.002, 2
+    refs = []
+    for i, n in enumerate(sizes):
+        r = u0[i]
+        for _ in range(k):
+            r = ons.ifrk2_step(r, nus[i], h)[0]
+        refs.append(r)
+    shapes = sorted({(a, v) for n in sizes for (a, E, v) in tk.tile_candidates(n, torch.float32, 8)})
+    assert len(shapes) >= 10
+    try:
+        for (nt, gv) in shapes:
+            for n in sizes:
+                cands = tk.tile_candidates(n, torch.float32, 8)
+                E = cands[0][1]
+                if (nt, E, gv) in cands:
+                    tk.tune_set(n, torch.float32, 8, nt, E, gv)
+                else:  # this thread count is not compiled for n: the default shape
+                    tk.tune_set(n, torch.float32, 8, 0, 0)
+            ens = tk.Ensemble(sizes, nus)
+            states = [torch.from_numpy(u.astype(np.complex64)).cuda() for u in u0]
+            ens.step(states, h, k)
+            for i, n in enumerate(sizes):
+                assert diag.rel_l2(states[i].cpu().numpy(), refs[i], n) <= 1e-4, (nt, gv, n)
+            ens.close()
+    finally:
+        tk.tune_clear()
