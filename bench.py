@@ -9,7 +9,8 @@ the per-pass kernel durations (HIP events on the launch stream), the roofline of
 dominant pass, the Navier-Stokes RK2 steps/s at 512^3 and the FP64 CPU oracle timed on
 the host cores on one 512^3 pair.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-ns]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-cpu-legs] [--no-ns]
+                      [--no-1024] [--no-extra]
 """
 import argparse
 import json
@@ -70,9 +71,14 @@ def ensemble_rate(tk, torch, steps=50):
             "ensemble_GBps": round(gbps, 1), "ensemble_frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 3)}
 
 
+MLP_FLOP_PER_POINT = 2 * (9 * 64 + 64 * 64 + 64 * 6)  # forward multiply-adds x 2
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
 def les_rate(tk, torch, steps=50):
     """64^3 LES steps/s with a closure network (random weights: the cost does not depend
-    on them) and without."""
+    on them) and without; the network's forward kernel (FP32 matrix cores) and its fused
+    loss + backward against the FP32 MFMA peak, at M = 64^3 points."""
     import numpy as np
     import synth
     Ws, bs = synth.mlp_init(seed=7)
@@ -83,23 +89,36 @@ def les_rate(tk, torch, steps=50):
     out = {}
     for name, model in (("les64_closure_steps_per_s", net), ("les64_plain_steps_per_s", None)):
         tk.les_step(ns, model, u, 1e-3, 2)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        tk.les_step(ns, model, u, 1e-3, steps)
-        torch.cuda.synchronize()
-        out[name] = round(steps / (time.perf_counter() - t), 1)
+        ms = event_time(torch, lambda: tk.les_step(ns, model, u, 1e-3, steps), 1)
+        out[name] = round(1e3 * steps / ms, 1)
     ns.close()
+    M = 64 ** 3
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x9 = torch.randn((9, M), generator=g, device="cuda")
+    t6 = torch.randn((6, M), generator=g, device="cuda")
+    y6 = torch.empty((6, M), device="cuda")
+    net.forward(x9, y6)
+    from paper_1805_07801_amd import les_train
+    ms_f = event_time(torch, lambda: net.forward(x9, y6), 50)
+    ms_b = event_time(torch, lambda: les_train._loss_grad_async(net, x9, t6), 20)
+    for name, ms, flop in (("mlp_forward", ms_f, MLP_FLOP_PER_POINT * M), ("mlp_loss_backward", ms_b, 3 * MLP_FLOP_PER_POINT * M)):
+        tf = flop / (ms * 1e-3) / 1e12
+        out[name + "_64cubed"] = {"ms": round(ms, 4), "GFLOP": round(flop / 1e9, 3), "TFLOPs": round(tf, 2),
+                                  "bound": "mfma", "peak_TFLOPs": MFMA_F32_PEAK_TFLOPS,
+                                  "frac": round(tf / MFMA_F32_PEAK_TFLOPS, 3)}
     return out
 
 
-def time_pairs(tk, torch, n, steps, warmup, seed=0, repeats=False):
+def time_pairs(tk, torch, n, steps, warmup, seed=0, repeats=False, overwrite=True):
     import numpy as np
     import synth
     f = synth.gaussian_field((n, n, n), seed)
     x = torch.from_numpy(f).cuda()
     del f
-    # c2r may use its input as workspace (as FFTW's c2r does): every pass stays in place
-    plan = tk.FFT3D(n, dtype=torch.float32, flags=tk.TK_FFT_TIMING | tk.TK_FFT_C2R_OVERWRITE)
+    # with overwrite, c2r may use its input as workspace (as FFTW's c2r does): every pass
+    # stays in place; else c2r preserves its input (the X inverse writes a workspace)
+    flags = tk.TK_FFT_TIMING | (tk.TK_FFT_C2R_OVERWRITE if overwrite else 0)
+    plan = tk.FFT3D(n, dtype=torch.float32, flags=flags)
     X = plan.empty_cplx()
     y = plan.empty_real()
     stream = torch.cuda.current_stream()
@@ -235,6 +254,22 @@ def traffic_from_profile(kernel_name):
     return rec.get(kernel_name.replace(" ", ""))
 
 
+def host_cores():
+    """(physical cores, logical CPUs) of this host from lscpu (sockets x cores per socket)."""
+    import subprocess
+    logical = os.cpu_count() or 0
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in txt.splitlines():
+            if ":" in line:
+                a, b = line.split(":", 1)
+                kv[a.strip()] = b.strip()
+        return int(kv["Socket(s)"]) * int(kv["Core(s) per socket"]), int(kv.get("CPU(s)", logical))
+    except Exception:
+        return None, logical
+
+
 def cpu_baseline(n=512, min_s=10.0, max_pairs=8):
     """The FP64 oracle (C, OpenMP over lines) on forward+inverse pairs of the same 512^3
     input, on the host cores: pairs are repeated until about min_s seconds of CPU work
@@ -252,6 +287,7 @@ def cpu_baseline(n=512, min_s=10.0, max_pairs=8):
         del F, g
     dt = sum(times) / len(times)
     R, C = field_bytes(n)
+    phys, logical = host_cores()
     return {
         "value": round((2 * R + 10 * C) / dt / 1e9, 3),
         "unit": "GB/s",
@@ -260,7 +296,73 @@ def cpu_baseline(n=512, min_s=10.0, max_pairs=8):
         "sample": "%d forward+inverse pairs of the 512^3 N(0,1) seed-0 field in FP64 (%.1f s in all)" % (
             len(times), sum(times)),
         "pair_s": round(dt, 3),
+        "host_physical_cores": phys,
+        "host_logical_cpus": logical,
     }
+
+
+_CPU_LEG = r"""
+import sys, time, json
+sys.path.insert(0, %(root)r)
+import numpy as np
+import synth
+from oracle import fft as offt, init as oinit, ns as ons
+leg = %(leg)r
+out = {"threads": offt.num_threads()}
+if leg.startswith("pair"):
+    n = int(leg[4:])
+    f = synth.gaussian_field((n, n, n), 0).astype(np.float64)
+    t = time.perf_counter()
+    g = offt.irfft3(offt.rfft3(f))
+    out["s"] = time.perf_counter() - t
+elif leg == "ns32":
+    u = offt.rfft3(synth.taylor_green(32))
+    t = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t < 2.0:
+        u = ons.ifrk2_step(u, 0.01, 0.01)[0]
+        k += 1
+    out["s"] = (time.perf_counter() - t) / k
+else:
+    n = 512
+    u = oinit.random_solenoidal(synth.gaussian_field((3, n, n, n), 1))
+    h = ons.cfl_dt(u, 0.5)
+    t = time.perf_counter()
+    ons.ifrk2_step(u, 1e-3, h)
+    out["s"] = time.perf_counter() - t
+print(json.dumps(out))
+"""
+
+
+def cpu_legs():
+    """The oracle on the rest of the workloads, each in a child process: one 512^3 pair on
+    one thread, one 1024^3 pair, and one IF-RK2 step of the 32^3 FP64 Taylor-Green case
+    (repeated for 2 s) and of the 512^3 decaying-turbulence field, on all threads."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    R, C = field_bytes(512)
+    R2, C2 = field_bytes(1024)
+    legs = {}
+    for name, leg, env in (("pair512_1thread", "pair512", {"OMP_NUM_THREADS": "1"}), ("pair1024", "pair1024", {}),
+                           ("ns32_fp64_step", "ns32", {}), ("ns512_step", "ns512", {})):
+        e = dict(os.environ)
+        e.update(env)
+        try:
+            r = subprocess.run([sys.executable, "-c", _CPU_LEG % {"root": here, "leg": leg}], capture_output=True,
+                               text=True, env=e, timeout=600)
+            d = json.loads(r.stdout.strip().splitlines()[-1])
+        except Exception as ex:  # a leg that cannot run here is reported, not fatal
+            legs[name] = {"error": str(ex)[:200]}
+            continue
+        rec = {"s": round(d["s"], 4), "threads": d["threads"]}
+        if leg == "pair512":
+            rec["GBps"] = round((2 * R + 10 * C) / d["s"] / 1e9, 3)
+        elif leg == "pair1024":
+            rec["GBps"] = round((2 * R2 + 10 * C2) / d["s"] / 1e9, 3)
+        else:
+            rec["steps_per_s"] = round(1.0 / d["s"], 4)
+        legs[name] = rec
+    return legs
 
 
 def ns_pass_bytes(n):
@@ -280,58 +382,93 @@ def ns_pass_bytes(n):
     }
 
 
+def event_time(torch, fn, reps):
+    """Mean ms of fn() over reps calls, HIP events on the current stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def pass_entry(ms, rw, peak=HBM_PEAK_GBPS):
+    """Per-kernel record: mean launch ms, algorithmic bytes, achieved GB/s and fraction of peak."""
+    r, w = rw
+    gbps = (r + w) / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "alg_MB": round((r + w) / 1e6, 1), "GBps": round(gbps, 1),
+            "frac_hbm_peak": round(gbps / peak, 3)}
+
+
 def ns_steps_per_s(tk, torch, n, steps, warmup):
-    """RK2 steps/s of the 512^3 decaying-turbulence configuration (CFL 0.5, nu 1e-3), and
-    the achieved HBM rate of each solver pass (HIP events around each pass)."""
+    """RK2 steps/s of the 512^3 decaying-turbulence configuration (CFL 0.5, nu 1e-3), timed
+    with HIP events on the launch stream over `steps` steps, and the achieved HBM rate of
+    each solver pass (HIP events around each pass)."""
     import synth
     ns = tk.NS(n, dtype=torch.float32, nu=1e-3, cfl=0.5)
     noise = torch.from_numpy(synth.gaussian_field((3, n, n, n), 1)).cuda()
     u = ns.init_random(noise)
     del noise
     ns.step(u, 0.0, warmup)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    ns.step(u, 0.0, steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    ms = event_time(torch, lambda: ns.step(u, 0.0, steps), 1)
     e = ns.diagnostics(u)["energy"]
     pt = ns.pass_times(u, iters=5)
     ns.close()
     passes = {}
-    for k, (r, w) in ns_pass_bytes(n).items():
-        ms = pt.get(k, 0.0)
-        if ms > 0:
-            gbps = (r + w) / (ms * 1e-3) / 1e9
-            passes[k] = {"ms": round(ms, 4), "alg_MB": round((r + w) / 1e6, 1), "GBps": round(gbps, 1),
-                         "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 3)}
-    return steps / dt, e, passes
+    for k, rw in ns_pass_bytes(n).items():
+        if pt.get(k, 0.0) > 0:
+            passes[k] = pass_entry(pt[k], rw)
+    return steps / (ms * 1e-3), e, passes
+
+
+def rbc_pass_bytes(n):
+    """Algorithmic HBM bytes (read, write) of each pass of the convection right-hand side at
+    n^3 FP32 (kept modes, transit rows of KZP), as for the solver passes: P1 4 -> 7 fields,
+    P2 7 fields, P3 7 -> 6, P4 6 fields, P5 6 transit fields plus theta and u_z of the input
+    state -> 4 output fields."""
+    K = (n - 1) // 3
+    KZC = K + 1
+    KZP = min((K + 1 + 15) // 16 * 16, n // 2 + 1)
+    kk = 2 * K + 1
+    c = 8
+    return {
+        "P1": (4 * kk * kk * KZP * c, 7 * n * kk * KZP * c),
+        "P2": (7 * n * KZP * kk * c, 7 * n * KZP * n * c),
+        "P3": (7 * n * n * KZC * c, 6 * n * n * KZP * c),
+        "P4": (6 * n * KZP * n * c, 6 * n * KZP * kk * c),
+        "P5": (6 * n * kk * KZC * c + 2 * kk * kk * KZC * c, 4 * kk * kk * KZC * c),
+    }
 
 
 def extension_rates(tk, torch, n=512):
     """The rows built beyond the hot path, each at 512^3 FP32: IF-RK4 steps/s of the
-    decaying-turbulence field (CFL 0.5), Rayleigh-Benard (FFF) IF-RK2 steps/s, the
-    sine-basis (SFF) transform pair, and the energy-transfer diagnostics."""
+    decaying-turbulence field (CFL 0.5), the energy-transfer diagnostics, Rayleigh-Benard
+    (FFF) IF-RK2 steps/s with the GB/s of each of its passes, and the sine-basis (SFF) and
+    all-sine/cosine (SSS) transform pairs with the GB/s of each pass, HIP events throughout."""
     import synth
     out = {}
+    R, C = field_bytes(n)
     noise = torch.from_numpy(synth.gaussian_field((3, n, n, n), 1)).cuda()
     ns = tk.NS(n, dtype=torch.float32, nu=1e-3, cfl=0.5, scheme="rk4")
     u = ns.init_random(noise)
     del noise
     ns.step(u, 0.0, 2)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    ns.step(u, 0.0, 10)
-    torch.cuda.synchronize()
-    out["ns512_rk4_steps_per_s"] = round(10 / (time.perf_counter() - t), 2)
-    # energy transfer T(s) and a 4-band shell-to-shell matrix of the same state
+    k = 20
+    out["ns512_rk4_steps_per_s"] = round(1e3 * k / event_time(torch, lambda: ns.step(u, 0.0, k), 1), 2)
+    # energy transfer T(s) (one right-hand side plus a shell reduction of u^* . N) and a
+    # 4-band shell-to-shell matrix of the same state
     nsh = tk.num_shells(n)
     ns.energy_transfer(u)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(3):
-        ns.energy_transfer(u)
-    torch.cuda.synchronize()
-    out["transfer512_ms"] = round((time.perf_counter() - t) / 3 * 1e3, 2)
+    ms = event_time(torch, lambda: ns.energy_transfer(u), 3)
+    pb = ns_pass_bytes(n)
+    K = (n - 1) // 3
+    kk = 2 * K + 1
+    rw = (sum(pb[p][0] for p in ("P1", "P2", "P3", "P4", "P5")) + 6 * kk * kk * (K + 1) * 8,
+          sum(pb[p][1] for p in ("P1", "P2", "P3", "P4", "P5")))
+    out["transfer512"] = pass_entry(ms, rw)
     bands = [min(3, s // 8) for s in range(nsh)]
     t = time.perf_counter()
     ns.shell_to_shell(u, bands, 4)
@@ -344,34 +481,38 @@ def extension_rates(tk, torch, n=512):
     g = torch.Generator(device="cuda").manual_seed(3)
     s4 = (torch.randn((4, n, n, n // 2 + 1), generator=g, device="cuda", dtype=torch.complex64) * 1e-6).contiguous()
     rbc.step(s4, 1e-4, 2)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    rbc.step(s4, 1e-4, 10)
-    torch.cuda.synchronize()
-    out["rbc512_rk2_steps_per_s"] = round(10 / (time.perf_counter() - t), 2)
+    k = 20
+    out["rbc512_rk2_steps_per_s"] = round(1e3 * k / event_time(torch, lambda: rbc.step(s4, 1e-4, k), 1), 2)
+    pt = rbc.pass_times(s4, iters=5)
+    out["rbc512_passes"] = {p: pass_entry(pt[p], rw) for p, rw in rbc_pass_bytes(n).items()}
     del s4, rbc
-    # sine basis along x (SFF): r2c + c2r pair
-    plan = tk.FFT3D(n, dtype=torch.float32, basis_x=1)
+    torch.cuda.empty_cache()
+    # sine basis along x (SFF), and cos / cos / sin on every axis (SSS): r2c + c2r pairs
     x = torch.randn((1, n, n, n), generator=g, device="cuda", dtype=torch.float32)
-    X = plan.empty_cplx()
-    y = plan.empty_real()
-    for _ in range(3):
-        plan.r2c(x, X)
-        plan.c2r(X, y)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(10):
-        plan.r2c(x, X)
-        plan.c2r(X, y)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / 10
-    R, C = field_bytes(n)
-    out["sff512_pair_ms"] = round(ms, 4)
-    out["sff512_pair_GBps"] = round((2 * R + 10 * C) / (ms * 1e-3) / 1e9, 1)
-    plan.close()
+    for name, kw, pbytes in (("sff512", {"basis_x": 1}, pass_bytes(n)),
+                             ("sss512", {"basis_x": 2, "basis_y": 2, "basis_z": 1},
+                              {p: 2 * R for p in ("z_r2c", "y_fwd", "x_fwd", "x_inv", "y_inv", "z_c2r")})):
+        plan = tk.FFT3D(n, dtype=torch.float32, flags=tk.TK_FFT_TIMING, **kw)
+        X = plan.empty_cplx()
+        y = plan.empty_real()
+
+        def pair():
+            plan.r2c(x, X)
+            plan.c2r(X, y)
+
+        for _ in range(3):
+            pair()
+        torch.cuda.synchronize()
+        plan.pass_times()
+        ms = event_time(torch, pair, 10)
+        pt = plan.pass_times()
+        names = ["z_r2c", "y_fwd", "x_fwd", "x_inv", "y_inv", "z_c2r"]
+        out[name + "_pair_ms"] = round(ms, 4)
+        out[name + "_pair_GBps"] = round(sum(pbytes.values()) / (ms * 1e-3) / 1e9, 1)
+        out[name + "_passes"] = {p: pass_entry(t, (pbytes[p] / 2, pbytes[p] / 2)) for p, t in zip(names, pt)}
+        plan.close()
+        del X, y
+    del x
     torch.cuda.empty_cache()
     return out
 
@@ -402,6 +543,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-legs", action="store_true", help="time only the 512^3 oracle pair on the host")
     ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--no-1024", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the ensemble and LES measurements")
@@ -456,6 +598,14 @@ def main():
         "tiles": desc,
         "roofline": roof,
     }
+    # the same pair with a c2r that preserves its input (the ABI default)
+    ms_p, passes_p, _, err_p, _ = time_pairs(tk, torch, n, max(10, args.steps // 2), 2, overwrite=False)
+    out["pair_input_preserving"] = {
+        "ms_per_pair": round(ms_p, 4),
+        "GBps": round((2 * R + 10 * C) / (ms_p * 1e-3) / 1e9, 1),
+        "passes_GBps": {k: round(pb[k] / (passes_p[k] * 1e-3) / 1e9, 1) for k in passes_p if passes_p[k] > 0},
+        "roundtrip_rel_l2": err_p,
+    }
     if not args.no_1024:
         n2 = 1024
         R2, C2 = field_bytes(n2)
@@ -471,7 +621,9 @@ def main():
             "roundtrip_rel_l2": err2,
         }
     if not args.no_ns and hasattr(tk, "NS"):
-        sps, e, nsp = ns_steps_per_s(tk, torch, 512, max(10, args.steps // 2), 2)
+        nsteps = max(50, args.steps // 2)
+        sps, e, nsp = ns_steps_per_s(tk, torch, 512, nsteps, 2)
+        out["ns512_timed_steps"] = nsteps
         out["ns512_rk2_steps_per_s"] = round(sps, 2)
         out["ns512_energy_after"] = e
         out["ns512_passes"] = nsp
@@ -484,6 +636,8 @@ def main():
             out["les64_over_dns512_speed"] = round(out["les64_closure_steps_per_s"] / out["ns512_rk2_steps_per_s"], 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(512)
+        if not args.no_cpu_legs:
+            out["cpu_baseline"]["legs"] = cpu_legs()
     print(json.dumps(out))
 
 

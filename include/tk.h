@@ -312,6 +312,12 @@ tk_status rbc_step(tk_rbc_t rbc, void *state, double dt, int nsteps, double *t_i
 tk_status rbc_diagnostics(tk_rbc_t rbc, const void *state, double *kinetic, double *thermal, double *uz_theta,
                           double *nusselt, void *stream);
 tk_status rbc_last_dt(tk_rbc_t rbc, double *dt);
+/* Mean duration in ms of each pass of one right-hand side of state s4 over iters runs timed
+ * with HIP events on `stream`: ms[0..4] = P1 (curl and x-inverse of u, theta: 4 -> 7 fields),
+ * P2 (y-inverse, 7 fields), P3 (z pass: 7 c2r, u x omega and u theta, 6 r2c), P4 (y-forward,
+ * 6 fields), P5 (x-forward, buoyancy, projection).  s4 is only read; the solver's workspace
+ * is overwritten.  Synchronises. */
+tk_status rbc_pass_times(tk_rbc_t rbc, const void *s4, int iters, float ms[5], void *stream);
 tk_status rbc_destroy(tk_rbc_t rbc);
 
 /* ------------------------------------------------------------------------------------

@@ -81,6 +81,7 @@ def _declare(L):
         "rbc_step": ([vp, vp, d, i, P(d), vp], i),
         "rbc_diagnostics": ([vp, vp, P(d), P(d), P(d), P(d), vp], i),
         "rbc_last_dt": ([vp, P(d)], i),
+        "rbc_pass_times": ([vp, vp, i, P(ctypes.c_float), vp], i),
         "rbc_destroy": ([vp], i),
         "ns_shell_to_shell": ([vp, vp, P(i), i, i, P(d), vp], i),
         "ns_batch_create": ([P(vp), i, P(i), P(d), i, d, u], i),
@@ -610,6 +611,13 @@ class RBC:
         v = [ctypes.c_double() for _ in range(4)]
         check(lib().rbc_diagnostics(self.h, _ptr(s4), *[ctypes.byref(x) for x in v], _stream(stream)))
         return {"kinetic": v[0].value, "thermal": v[1].value, "uz_theta": v[2].value, "nusselt": v[3].value}
+
+    def pass_times(self, s4, iters=5, stream=None):
+        """Mean ms of the right-hand side's passes P1..P5 (see rbc_pass_times)."""
+        self._check(s4)
+        t = (ctypes.c_float * 5)()
+        check(lib().rbc_pass_times(self.h, _ptr(s4), iters, t, _stream(stream)))
+        return dict(zip(["P1", "P2", "P3", "P4", "P5"], list(t)))
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -82,15 +82,23 @@ static void rbc_free(tk_rbc_s *p) {
 }
 
 // One right-hand side of uin (4 fields): P1..P5 with the stage combine `mode`.
+// ev (optional, 6 events): recorded before P1 and after each pass.
 static tk_status rbc_rhs_eval(tk_rbc_s *p, const void *uin, void *u, void *out, int mode, bool first_stage,
-                              hipStream_t s) {
+                              hipStream_t s, hipEvent_t *ev = nullptr) {
     const NsGrid &g = p->g;
     const int n = g.n;
+    auto mark = [&](int i) -> tk_status {
+        if (ev) TK_HIP_CHECK(hipEventRecord(ev[i], s));
+        return TK_OK;
+    };
+    TK_TRY(mark(0));
     g.nk->p1r(uin, p->w7, g.K, g.KZC, g.ax.twx, p->ka, s);
     TK_TRY(launch_check("rbc P1"));
+    TK_TRY(mark(1));
     StridedArgs y2{p->w7, p->w7, 7L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 1, 1.0, g.K, -1};
     g.ky->fn(y2, s);
     TK_TRY(launch_check("rbc P2"));
+    TK_TRY(mark(2));
     g.nk->p3r(p->w7, (long)n * n, g.KZC, g.ax.twz, first_stage ? p->umax_part : nullptr, s);
     TK_TRY(launch_check("rbc P3"));
     if (first_stage) {
@@ -98,11 +106,14 @@ static tk_status rbc_rhs_eval(tk_rbc_s *p, const void *uin, void *u, void *out, 
         hipLaunchKernelGGL(k_ns_set_h, dim3(1), dim3(1024), 0, s, p->st, p->umax_part, nparts);
         TK_TRY(launch_check("rbc step size"));
     }
+    TK_TRY(mark(3));
     StridedArgs y4{p->w7, p->w7, 6L * n * g.KZP, g.KZP, (long)n * g.KZP, g.KZP, g.ax.twy, 0, 1.0, -1, g.K};
     g.ky->fn(y4, s);
     TK_TRY(launch_check("rbc P4"));
+    TK_TRY(mark(4));
     g.nk->p5r(p->w7, uin, u, p->aux, p->ust, out, p->st, p->nu_a, p->kap_a, p->ka, mode, g.K, g.KZC, g.ax.twx, s);
-    return launch_check("rbc P5");
+    TK_TRY(launch_check("rbc P5"));
+    return mark(5);
 }
 
 static tk_status rbc_one_step(tk_rbc_s *p, void *u, hipStream_t s) {
@@ -154,6 +165,34 @@ extern "C" tk_status rbc_rhs(tk_rbc_t p, const void *s4, void *rhs_out, void *st
     else hipLaunchKernelGGL(k_zero<double2>, dim3(4096), dim3(256), 0, s, (double2 *)rhs_out, nvals);
     TK_TRY(launch_check("zero rhs"));
     return rbc_rhs_eval(p, s4, const_cast<void *>(s4), rhs_out, NS_RHS, false, s);
+}
+
+extern "C" tk_status rbc_pass_times(tk_rbc_t p, const void *s4, int iters, float ms[5], void *stream) {
+    if (!p || !s4 || !ms) return fail(TK_EINVAL, "NULL argument");
+    if (iters < 1) return fail(TK_EINVAL, "iters must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[6] = {};
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) hipEventDestroy(f);
+            return fail(TK_EHIP, "event creation failed");
+        }
+    double acc[5] = {0, 0, 0, 0, 0};
+    tk_status st = TK_OK;
+    for (int it = 0; it < iters && st == TK_OK; ++it) {
+        // one right-hand side into the stage-input buffer; the state is only read
+        st = rbc_rhs_eval(p, s4, const_cast<void *>(s4), p->ust, NS_RHS, false, s, ev);
+        if (st == TK_OK && hipEventSynchronize(ev[5]) != hipSuccess) st = fail(TK_EHIP, "event synchronisation failed");
+        for (int i = 0; i < 5 && st == TK_OK; ++i) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = fail(TK_EHIP, "event timing failed");
+            acc[i] += t;
+        }
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    for (int i = 0; i < 5; ++i) ms[i] = (float)(acc[i] / iters);
+    return st;
 }
 
 extern "C" tk_status rbc_step(tk_rbc_t p, void *u, double dt, int nsteps, double *t_inout, void *stream) {
