@@ -470,8 +470,15 @@ __device__ __forceinline__ void ns_p5_tile(const V2<T> *c3, const V2<T> *__restr
                 continue;
             }
             const double a = nu * (double)k2 * h;
-            const T e1 = (T)exp(-a);
-            const T e2 = (T)exp(-0.5 * a);
+            T e1, e2;
+            if constexpr (sizeof(T) == 4) {
+                // FP32: one single-precision exponential (relative error ~1e-7), E = E2^2
+                e2 = expf((float)(-0.5 * a));
+                e1 = e2 * e2;
+            } else {
+                e1 = exp(-a);
+                e2 = exp(-0.5 * a);
+            }
             const T th = (T)h;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
@@ -637,8 +644,14 @@ __device__ __forceinline__ void rbc_p5_tile(const V2<T> *__restrict__ c6, const 
                 for (int f = 0; f < 4; ++f) *at(out, f) = nn[f];
                 continue;
             }
-            const T eu = (T)exp(-nu_a * (double)k2 * h);
-            const T et = (T)exp(-kap_a * (double)k2 * h);
+            T eu, et;
+            if constexpr (sizeof(T) == 4) {
+                eu = expf((float)(-nu_a * (double)k2 * h));
+                et = expf((float)(-kap_a * (double)k2 * h));
+            } else {
+                eu = exp(-nu_a * (double)k2 * h);
+                et = exp(-kap_a * (double)k2 * h);
+            }
             const T th_ = (T)h;
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
