@@ -219,8 +219,12 @@ __device__ __forceinline__ void stage_exchange(V2<T> (&v)[E], V2<T> *d, int jt) 
 // SPLIT: exchange the real parts, then the imaginary parts, through an LDS line of scalars
 // (d is then a T pointer in disguise, element e at ((T *)d)[lds_at<ES>(e)]): half the LDS
 // of a column tile, so more workgroups fit on a CU, for two more barriers per exchange.
-template <typename T, int L, int E, int ES, int TS = 1, int S = 0, bool TWP = false, bool SPLIT = false>
-__device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw) {
+// RS: the stage whose twiddles the caller holds in registers (wr[m - 1] for leg m; -1: none).
+// Allowed only for a stage with one butterfly per thread (E == R there), whose twiddles
+// depend on the lane alone: see stage_twiddles.
+template <typename T, int L, int E, int ES, int TS = 1, int S = 0, bool TWP = false, bool SPLIT = false, int RS = -1>
+__device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const V2<T> *tw,
+                                         const V2<T> *wr = nullptr) {
     using C = V2<T>;
     constexpr RPlan P = make_rplan(L, E);
     constexpr int R = P.r[S];
@@ -228,11 +232,15 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
     constexpr int NB = E / R;
     constexpr int TPL = L / E;
     static_assert(ES != 1 || (TPL <= 64 && 64 % TPL == 0), "a contiguous line must sit inside one wavefront");
+    static_assert(S != RS || NB == 1, "register twiddles need one butterfly per thread at that stage");
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = jt + b * TPL;
         const int k = j % NS;
-        if constexpr (NS > 1) {
+        if constexpr (NS > 1 && S == RS) {
+#pragma unroll
+            for (int m = 1; m < R; ++m) v[b + m * NB] = cmul(v[b + m * NB], wr[m - 1]);
+        } else if constexpr (NS > 1) {
             if constexpr (TWP) {
                 // leg m takes W^m, W = W_{NS R}^k: one table read, the powers by
                 // multiplication (R - 2 complex products instead of R - 2 more LDS reads;
@@ -253,8 +261,32 @@ __device__ __forceinline__ void line_fft(V2<T> (&v)[E], V2<T> *d, int jt, const 
     }
     if constexpr (S + 1 < P.n) {
         stage_exchange<T, L, E, ES, S, SPLIT>(v, d, jt);
-        line_fft<T, L, E, ES, TS, S + 1, TWP, SPLIT>(v, d, jt, tw);
+        line_fft<T, L, E, ES, TS, S + 1, TWP, SPLIT, RS>(v, d, jt, tw, wr);
     }
+}
+
+// The first stage after stage 0 whose butterflies are one per thread (E == R), or -1: its
+// twiddles W_{NS R}^{(jt mod NS) m} depend on the lane alone, so a caller that runs many
+// transforms can hold them in registers.
+template <int L, int E> constexpr int lane_twiddle_stage() {
+    constexpr RPlan P = make_rplan(L, E);
+    for (int s = 1; s < P.n; ++s)
+        if (P.r[s] == E) return s;
+    return -1;
+}
+
+// wr[m - 1] = W_{NS R}^{k m}, k = jt mod NS, for stage S (one table read, the powers by
+// multiplication); tw is the W_{L TS}^j table the transforms use.
+template <typename T, int L, int E, int TS, int S>
+__device__ __forceinline__ void stage_twiddles(int jt, const V2<T> *tw, V2<T> (&wr)[E - 1]) {
+    constexpr RPlan P = make_rplan(L, E);
+    constexpr int R = P.r[S];
+    constexpr int NS = rplan_span(P, S);
+    static_assert(R == E, "one butterfly per thread");
+    const V2<T> w = tw[(jt % NS) * (L / (NS * R)) * TS];
+    wr[0] = w;
+#pragma unroll
+    for (int m = 1; m < R - 1; ++m) wr[m] = cmul(wr[m - 1], w);
 }
 
 // ---- mirror exchange ---------------------------------------------------------------------------------

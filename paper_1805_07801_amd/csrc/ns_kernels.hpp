@@ -252,12 +252,18 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     C uu[3][E], c[NOUT][E];
     // the next field's samples are loaded before the current field is transformed, so the
     // loads overlap the transform (the exchange waits only on LDS traffic)
+    // Unguarded loads: lanes of an invalid line read line 0 and store nothing; register
+    // blocks wholly past the kept columns are zero without a load, and only the block that
+    // straddles KZC compares (KZC is the 2/3 rule's (N - 1) / 3 + 1 for every caller).
+    constexpr int KZC0 = (N - 1) / 3 + 1;
     auto load = [&](C(&x)[E], int f) {
         const C *s = w6 + f * FS + (valid ? l : 0) * KZP;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int k = jt + i * TPL;
-            x[i] = (valid && k < KZC) ? s[k] : mk<T>(0, 0);
+            if (i * TPL >= KZC0) x[i] = mk<T>(0, 0);
+            else if ((i + 1) * TPL <= KZC0) x[i] = s[k];
+            else x[i] = k < KZC0 ? s[k] : mk<T>(0, 0);
         }
     };
     C nx[E];
@@ -266,7 +272,12 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     // (twiddles held in registers for all nine transforms instead of the LDS table cost
     // occupancy and measured no faster at 512^3)
     auto split_tw = [&](int i) { return tw[jt + i * TPL]; };
-    auto xform = [&](C(&v)[E]) { line_fft<T, L, E, 1, 2, 0, true>(v, d, jt, tw); };
+    // the twiddles of the one stage that has a single butterfly per thread depend on the lane
+    // alone: formed once, in registers, for all nine transforms
+    constexpr int RS = lane_twiddle_stage<L, E>();
+    C wr[E - 1];
+    if constexpr (RS > 0) stage_twiddles<T, L, E, 2, RS>(jt, tw, wr);
+    auto xform = [&](C(&v)[E]) { line_fft<T, L, E, 1, 2, 0, true, false, RS>(v, d, jt, tw, wr); };
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
         C v[E], xm[E];
@@ -277,10 +288,14 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
         mirror<T, L, E>(v, xm, jt);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const int k = jt + i * TPL;
+            // k = jt + i TPL is 0 only in register 0 of lane 0 of the line
+            const bool k0 = i == 0 && jt == 0;
             C xk = v[i];
-            C xc = k == 0 ? mk<T>(0, 0) : cconj(xm[i]);
-            if (k == 0) xk.y = 0;
+            C xc = cconj(xm[i]);
+            if (i == 0) {
+                xc = k0 ? mk<T>(0, 0) : xc;
+                xk.y = k0 ? (T)0 : xk.y;
+            }
             const C a = cadd(xk, xc);
             const C b = cmul(cconj(split_tw(i)), csub(xk, xc));
             v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
