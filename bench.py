@@ -227,17 +227,18 @@ def copy_bandwidth(torch, nbytes=1 << 29, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def traffic_from_profile(kernel_name):
-    """HBM bytes per launch of the named kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
-    None if the summary does not cover this kernel or the kernel sources changed since."""
+def profile_record(summary, sources, key, kernel_name):
+    """A per-launch figure of the named kernel from a committed rocprofv3 counter summary
+    (lines `key <kernel name without spaces> <value>`), or None if the summary does not
+    cover this kernel or the kernel sources changed since the counters were taken (the
+    summary's `source_digest` line: sha256 of the listed sources, first 16 hex digits)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "fft3d_pair_512_pmc.txt")
+    path = os.path.join(here, "profiles", summary)
     if not os.path.exists(path):
         return None
     src = b""
-    for f in ("fft_core.hpp", "fft_kernels.hpp"):
+    for f in sources:
         with open(os.path.join(here, "paper_1805_07801_amd", "csrc", f), "rb") as fh:
             src += fh.read()
     digest = hashlib.sha256(src).hexdigest()[:16]
@@ -247,11 +248,38 @@ def traffic_from_profile(kernel_name):
             parts = line.split()
             if len(parts) >= 3 and parts[0] == "source_digest":
                 rec["digest"] = parts[1]
-            if len(parts) >= 3 and parts[0] == "traffic_bytes_per_launch":
+            if len(parts) >= 3 and parts[0] == key:
                 rec[parts[1]] = float(parts[2])
     if rec.get("digest") != digest:
         return None
     return rec.get(kernel_name.replace(" ", ""))
+
+
+def traffic_from_profile(kernel_name):
+    """HBM bytes per launch of the named pair kernel (FETCH_SIZE + WRITE_SIZE, each scaled
+    by the copy-kernel calibration)."""
+    return profile_record("fft3d_pair_512_pmc.txt", ("fft_core.hpp", "fft_kernels.hpp"),
+                          "traffic_bytes_per_launch", kernel_name)
+
+
+# wave64 VALU instructions per second the chip can issue: 256 CUs x 4 SIMDs x 2.4 GHz, one
+# wave64 instruction per SIMD every 4 cycles (= 39.3 T lane operations/s)
+VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4
+
+
+def p3_alu_roofline(ms):
+    """ALU roofline of the fused Z pass of the 512^3 solver (six inverse and three forward
+    line transforms with the products between them, bound by vector ALU issue): VALU
+    instructions per launch from the committed counter summary / the live mean launch time."""
+    name = "k_ns_p3<float, 256, 8, 8, false>"
+    n_inst = profile_record("ns512_counters.txt", ("fft_core.hpp", "ns_kernels.hpp"),
+                            "valu_instructions_per_launch", name)
+    if n_inst is None:
+        return None
+    achieved = n_inst / (ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": VALU_PEAK_GIPS,
+            "unit": "G wave64 VALU instructions/s", "frac": round(achieved / VALU_PEAK_GIPS, 4),
+            "instructions_per_launch": n_inst, "kernel_name": name}
 
 
 def host_cores():
@@ -421,6 +449,10 @@ def ns_steps_per_s(tk, torch, n, steps, warmup):
     for k, rw in ns_pass_bytes(n).items():
         if pt.get(k, 0.0) > 0:
             passes[k] = pass_entry(pt[k], rw)
+    if n == 512 and "P3" in passes:
+        alu = p3_alu_roofline(pt["P3"])
+        if alu:
+            passes["P3"]["alu_roofline"] = alu
     return steps / (ms * 1e-3), e, passes
 
 
