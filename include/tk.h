@@ -379,8 +379,11 @@ typedef struct {
 tk_status sgs_mlp_forward(const tk_mlp *w, const float *x9, float *y6, long M, void *stream);
 
 /* grad (device, TK_MLP_NPARAM FP32) = sum over the M points of (d f(x9/in_scale) / d theta)^T
- * dy6, with dy6 the gradient with respect to the normalised network outputs.  The point
- * sums are formed per slice and added over slices in a fixed order in FP64. */
+ * dy6, with dy6 the gradient with respect to the normalised network outputs.  Each
+ * workgroup sums its points in FP32 (a fixed order), and the workgroups' partial sums are
+ * added in a fixed order in FP64, so a result is reproducible on one device.  The partial
+ * sums live in a per-device library buffer: backward calls that overlap on one device
+ * (concurrent streams, or host threads) must be serialised by the caller. */
 tk_status sgs_mlp_backward(const tk_mlp *w, const float *x9, const float *dy6, long M, float *grad,
                            void *stream);
 

@@ -7,7 +7,6 @@
 // FP32.  Flat parameter order W1[64][9], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <new>
 
 #include "ns_api.hpp"
@@ -157,164 +156,314 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
     }
 }
 
-// ---- loss and backward ------------------------------------------------------------------------------
-// Per point: forward, dy (given, or 2 (y - t/out_scale) / (6 M) from targets), backprop to
-// da2 = (W3^T dy) gelu'(a2) and da1 = (W2^T da2) gelu'(a1).  Writes the factors of the
-// per-parameter sums: X[9][M] (normalised input), H1[64][M], H2[64][M], DA1[64][M],
-// DA2[64][M], DY[6][M]; loss partial sums per block (FP64).
-struct BwdBufs {
-    float *X, *H1, *H2, *DA1, *DA2, *DY;
-};
+// ---- loss and backward on the matrix cores -----------------------------------------------------------
+// One wavefront walks 16-point blocks as the forward does, and per block:
+//   the forward of k_mlp_fwd, keeping gelu'(a1) and gelu'(a2) beside h1 and h2;
+//   dy = 2 (y - t / out_scale) / (6 M) with loss += (y - t / out_scale)^2, or the given dy;
+//   da2 = (W3^T dy) gelu'(a2) and da1 = (W2^T da2) gelu'(a1), products in the forward's
+//   layout (the transposed weights are per-lane A operands too);
+//   the weight gradients, sums over points: gW1 += da1 x^T, gW2 += da2 h1^T, gW3 += dy h2^T.
+// In those the contraction runs over the block's 16 points, four per instruction, whereas
+// the activations sit with one point per lane: the factors go through the wavefront's own
+// LDS as [feature][point] tiles and come back with the points along the K slots.  A lane
+// reads (feature 16 t + c, point 4 s + kk), so accumulator tile (t, t') holds, at lane
+// (kk, c), gradient entries (16 t + 4 kk + r, 16 t' + c).  The bias gradients are per-lane
+// sums of da1, da2 and dy, reduced over the 16 lanes of a point block at the end.  Every
+// workgroup leaves one partial sum per parameter (its waves added in a fixed order).
+constexpr int TS = 20;  // row stride of the LDS tiles: at most two lanes of a wavefront per bank
+constexpr int WT = (4 * 64 + 2 * 16) * TS;
 
-__global__ __launch_bounds__(MB) void k_mlp_bwd_a(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
-                                                 const float *__restrict__ t6, const float *__restrict__ dy6,
-                                                 long M, float in_inv, float out_inv, BwdBufs B,
-                                                 double *__restrict__ lpart) {
-    __shared__ float w[NP];
-    __shared__ double sh[MB / 64];
-    load_weights(w, wb);
-    const float dscale = 2.0f / (6.0f * (float)M);
-    double lacc = 0;
-    for (long p = (long)blockIdx.x * MB + threadIdx.x; p < M; p += (long)gridDim.x * MB) {
-        float x[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            x[c] = x9[c * M + p] * in_inv;
-            B.X[c * M + p] = x[c];
-        }
-        // h1 = gelu(a1) stays in registers; gelu'(a1) is parked in DA1 until dh1 is known
-        float h1[64];
-#pragma unroll
-        for (int o = 0; o < 64; ++o) {
-            float a = w[OB1 + o];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) a = fmaf(w[OW1 + o * 9 + c], x[c], a);
-            h1[o] = gelu(a);
-            B.H1[o * M + p] = h1[o];
-            B.DA1[o * M + p] = gelu_grad(a);
-        }
-        float y[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) y[q] = w[OB3 + q];
-        // a2 kept only through H2 / gelu'(a2): store gelu'(a2) in DA2 temporarily
-#pragma unroll 4
-        for (int o = 0; o < 64; ++o) {
-            float a = w[OB2 + o];
-#pragma unroll
-            for (int i = 0; i < 64; ++i) a = fmaf(w[OW2 + o * 64 + i], h1[i], a);
-            const float h2 = gelu(a);
-            B.H2[o * M + p] = h2;
-            B.DA2[o * M + p] = gelu_grad(a);
-#pragma unroll
-            for (int q = 0; q < 6; ++q) y[q] = fmaf(w[OW3 + q * 64 + o], h2, y[q]);
-        }
-        float dy[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            if (t6) {
-                const float d = y[q] - t6[q * M + p] * out_inv;
-                lacc += (double)d * d;
-                dy[q] = d * dscale;
-            } else {
-                dy[q] = dy6[q * M + p];
-            }
-            B.DY[q * M + p] = dy[q];
-        }
-        // da2 = (W3^T dy) * gelu'(a2); dh1 = W2^T da2
-        float dh1[64];
-#pragma unroll
-        for (int i = 0; i < 64; ++i) dh1[i] = 0.f;
-#pragma unroll 4
-        for (int o = 0; o < 64; ++o) {
-            float g = 0.f;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) g = fmaf(w[OW3 + q * 64 + o], dy[q], g);
-            const float da2 = g * B.DA2[o * M + p];
-            B.DA2[o * M + p] = da2;
-#pragma unroll
-            for (int i = 0; i < 64; ++i) dh1[i] = fmaf(w[OW2 + o * 64 + i], da2, dh1[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 64; ++i) B.DA1[i * M + p] = dh1[i] * B.DA1[i * M + p];
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+__global__ __launch_bounds__(MB) void k_mlp_bwd(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
+                                               const float *__restrict__ t6, const float *__restrict__ dy6, long M,
+                                               float in_inv, float out_inv, float *__restrict__ part,
+                                               double *__restrict__ lpart) {
+    constexpr int NW = MB / 64;
+    __shared__ float tiles[NW * WT];
+    // W2 as the A operands of layer 2 (forward) and of W2^T da2 (backward), four steps r
+    // per lane in one 16-byte read: [q][qi][lane][r]
+    __shared__ float4 sW2[16 * 64], sW2t[16 * 64];
+    __shared__ double sh[NW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int kk = lane >> 4, c = lane & 15;
+    float *sH1 = tiles + wid * WT, *sH2 = sH1 + 64 * TS, *sD1 = sH2 + 64 * TS, *sD2 = sD1 + 64 * TS;
+    float *sX = sD2 + 64 * TS, *sDY = sX + 16 * TS;
+    auto w = [&](int i) { return bf16_f32(wb[i]); };
+    // forward operands as in k_mlp_fwd (W2's from the LDS); backward ones:
+    //   W3^T dy, step s:       A[c][kk] = W3[4 s + kk][16 q + c] (outputs 6, 7 zero)
+    //   W2^T da2, step (qi, r): A[c][kk] = W2[16 qi + 4 kk + r][16 q + c]
+    for (int e = threadIdx.x; e < 16 * 64; e += MB) {
+        const int q = e >> 8, qi = (e >> 6) & 3, l = e & 63, lk = l >> 4, lc = l & 15;
+        float4 f, g;
+        f.x = w(OW2 + (16 * q + lc) * 64 + 16 * qi + 4 * lk + 0);
+        f.y = w(OW2 + (16 * q + lc) * 64 + 16 * qi + 4 * lk + 1);
+        f.z = w(OW2 + (16 * q + lc) * 64 + 16 * qi + 4 * lk + 2);
+        f.w = w(OW2 + (16 * q + lc) * 64 + 16 * qi + 4 * lk + 3);
+        g.x = w(OW2 + (16 * qi + 4 * lk + 0) * 64 + 16 * q + lc);
+        g.y = w(OW2 + (16 * qi + 4 * lk + 1) * 64 + 16 * q + lc);
+        g.z = w(OW2 + (16 * qi + 4 * lk + 2) * 64 + 16 * q + lc);
+        g.w = w(OW2 + (16 * qi + 4 * lk + 3) * 64 + 16 * q + lc);
+        sW2[e] = f;
+        sW2t[e] = g;
     }
+    __syncthreads();
+    float a1[4][3], a3[16], a3t[4][2];
+    v4f b1[4], b2[4], b3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) a1[q][t] = (4 * t + kk < 9) ? w(OW1 + (16 * q + c) * 9 + 4 * t + kk) : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b1[q][r] = w(OB1 + 16 * q + 4 * kk + r);
+            b2[q][r] = w(OB2 + 16 * q + 4 * kk + r);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) a3t[q][s] = (4 * s + kk < 6) ? w(OW3 + (4 * s + kk) * 64 + 16 * q + c) : 0.f;
+    }
+#pragma unroll
+    for (int qi = 0; qi < 4; ++qi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a3[4 * qi + r] = c < 6 ? w(OW3 + c * 64 + 16 * qi + 4 * kk + r) : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b3[r] = (4 * kk + r < 6) ? w(OB3 + 4 * kk + r) : 0.f;
+    // rows 12..15 of the input tile and 8..15 of the output-gradient tile stay zero
+    for (int i = lane; i < 32 * TS; i += 64) sX[i] = 0.f;
+
+    const v4f z4 = {0.f, 0.f, 0.f, 0.f};
+    v4f gw1[4], gw2[4][4], gw3[4];
+    float gb1[4][4], gb2[4][4], gb3[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gw1[q] = z4;
+        gw3[q] = z4;
+        gb3[q] = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            gw2[q][r] = z4;
+            gb1[q][r] = 0.f;
+            gb2[q][r] = 0.f;
+        }
+    }
+    double lacc = 0;
+    const float dscale = 2.0f / (6.0f * (float)M);
+    const long nblk = (M + 15) / 16;
+    const long wv = (long)blockIdx.x * NW + wid;
+    const long nwv = (long)gridDim.x * NW;
+    // a block's inputs and targets (or given output gradients): lane (kk, c) takes input
+    // features 4 t + kk and outputs 4 kk + r of point c
+    auto load = [&](long blk, float (&xv)[3], float (&tv)[4]) {
+        const long p = blk * 16 + c;
+        const bool in = blk < nblk && p < M;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) xv[t] = (in && 4 * t + kk < 9) ? x9[(4 * t + kk) * M + p] * in_inv : 0.f;
+        const float *src = t6 ? t6 : dy6;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[r] = (in && 4 * kk + r < 6) ? src[(4 * kk + r) * M + p] : 0.f;
+    };
+    float xn[3], tn[4];
+    load(wv, xn, tn);
+    for (long blk = wv; blk < nblk; blk += nwv) {
+        const bool in = blk * 16 + c < M;
+        float xv[3] = {xn[0], xn[1], xn[2]};
+        float tv[4] = {tn[0], tn[1], tn[2], tn[3]};
+        load(blk + nwv, xn, tn);  // the next block's, in flight during this one
+        // forward
+        v4f d1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d1[q] = b1[q];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) d1[q] = mfma4(a1[q][t], xv[t], d1[q]);
+        }
+        float h1[4][4], g1[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                h1[q][r] = gelu(d1[q][r]);
+                g1[q][r] = gelu_grad(d1[q][r]);
+            }
+        v4f d2[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d2[q] = b2[q];
+#pragma unroll
+            for (int qi = 0; qi < 4; ++qi) {
+                const float4 a = sW2[(4 * q + qi) * 64 + lane];
+                d2[q] = mfma4(a.x, h1[qi][0], d2[q]);
+                d2[q] = mfma4(a.y, h1[qi][1], d2[q]);
+                d2[q] = mfma4(a.z, h1[qi][2], d2[q]);
+                d2[q] = mfma4(a.w, h1[qi][3], d2[q]);
+            }
+        }
+        float h2[4][4], g2[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                h2[q][r] = gelu(d2[q][r]);
+                g2[q][r] = gelu_grad(d2[q][r]);
+            }
+        v4f d3q[4];
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            d3q[qi] = qi == 0 ? b3 : z4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d3q[qi] = mfma4(a3[4 * qi + r], h2[qi][r], d3q[qi]);
+        }
+        const v4f d3 = (d3q[0] + d3q[1]) + (d3q[2] + d3q[3]);
+        float dyv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float g = 0.f;
+            if (in && 4 * kk + r < 6) {
+                if (t6) {
+                    const float d = d3[r] - tv[r] * out_inv;
+                    lacc += (double)d * d;
+                    g = d * dscale;
+                } else {
+                    g = tv[r];
+                }
+            }
+            dyv[r] = g;
+            gb3[r] += g;
+        }
+        // the block's tiles as [feature][point]
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sH1[(16 * q + 4 * kk + r) * TS + c] = h1[q][r];
+                sH2[(16 * q + 4 * kk + r) * TS + c] = h2[q][r];
+            }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) sX[(4 * t + kk) * TS + c] = xv[t];
+        if (kk < 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sDY[(4 * kk + r) * TS + c] = dyv[r];
+        }
+        wave_lds_sync();
+        // da2 = (W3^T dy) gelu'(a2); da1 = (W2^T da2) gelu'(a1)
+        const float bdy0 = sDY[kk * TS + c], bdy1 = sDY[(4 + kk) * TS + c];
+        float da2[4][4], da1[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v4f e = mfma4(a3t[q][0], bdy0, z4);
+            e = mfma4(a3t[q][1], bdy1, e);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) da2[q][r] = e[r] * g2[q][r];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v4f e = z4;
+#pragma unroll
+            for (int qi = 0; qi < 4; ++qi) {
+                const float4 a = sW2t[(4 * q + qi) * 64 + lane];
+                e = mfma4(a.x, da2[qi][0], e);
+                e = mfma4(a.y, da2[qi][1], e);
+                e = mfma4(a.z, da2[qi][2], e);
+                e = mfma4(a.w, da2[qi][3], e);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) da1[q][r] = e[r] * g1[q][r];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gb1[q][r] += da1[q][r];
+                gb2[q][r] += da2[q][r];
+                sD1[(16 * q + 4 * kk + r) * TS + c] = da1[q][r];
+                sD2[(16 * q + 4 * kk + r) * TS + c] = da2[q][r];
+            }
+        wave_lds_sync();
+        // weight gradients: the block's points as the contraction, four per step
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int pc = 4 * s + kk;
+            const float xb = sX[c * TS + pc];
+            const float ya = sDY[c * TS + pc];
+            float h1b[4], h2b[4], d1a[4], d2a[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                h1b[t] = sH1[(16 * t + c) * TS + pc];
+                h2b[t] = sH2[(16 * t + c) * TS + pc];
+                d1a[t] = sD1[(16 * t + c) * TS + pc];
+                d2a[t] = sD2[(16 * t + c) * TS + pc];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                gw1[t] = mfma4(d1a[t], xb, gw1[t]);
+                gw3[t] = mfma4(ya, h2b[t], gw3[t]);
+#pragma unroll
+                for (int t2 = 0; t2 < 4; ++t2) gw2[t][t2] = mfma4(d2a[t], h1b[t2], gw2[t][t2]);
+            }
+        }
+        wave_lds_sync();  // this block's tile reads are done before the next block writes
+    }
+    // bias gradients: sums over the 16 lanes of each point block
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gb1[q][r] += __shfl_xor(gb1[q][r], o, 64);
+                gb2[q][r] += __shfl_xor(gb2[q][r], o, 64);
+            }
+            gb3[q] += __shfl_xor(gb3[q], o, 64);
+        }
+    }
+    // the workgroup's partial sums: wave 0 writes, waves 1.. add in order
+    float *red = tiles;
+    __syncthreads();
+    for (int v = 0; v < NW; ++v) {
+        if (wid == v) {
+            auto put = [&](int j, float x) { red[j] = v == 0 ? x : red[j] + x; };
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = 16 * t + 4 * kk + r;
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2) put(OW2 + o * 64 + 16 * t2 + c, gw2[t][t2][r]);
+                    if (c < 9) put(OW1 + o * 9 + c, gw1[t][r]);
+                    if (4 * kk + r < 6) put(OW3 + (4 * kk + r) * 64 + 16 * t + c, gw3[t][r]);
+                    if (c == 0) {
+                        put(OB1 + o, gb1[t][r]);
+                        put(OB2 + o, gb2[t][r]);
+                    }
+                }
+            if (c == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (4 * kk + r < 6) put(OB3 + 4 * kk + r, gb3[r]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < NP; j += MB) part[(long)blockIdx.x * NP + j] = red[j];
     if (t6) {
         lacc = block_sum(lacc, sh);
         if (threadIdx.x == 0) lpart[blockIdx.x] = lacc;
     }
 }
 
-// Per-slice partial sums of every parameter's gradient:
-//   W1[o][c]: sum_p DA1[o][p] X[c][p]    b1[o]: sum_p DA1[o][p]
-//   W2[o][i]: sum_p DA2[o][p] H1[i][p]   b2[o]: sum_p DA2[o][p]
-//   W3[q][i]: sum_p DY[q][p]  H2[i][p]   b3[q]: sum_p DY[q][p]
-// A slice of points is staged through LDS in chunks of PC points; thread t owns
-// parameters t, t + 256, ... (at most 21).
-constexpr int PC = 32;
-constexpr int PPT = (NP + MB - 1) / MB;
-
-__global__ __launch_bounds__(MB) void k_mlp_bwd_b(BwdBufs B, long M, long slice, float *__restrict__ part) {
-    __shared__ float sX[9][PC], sH1[64][PC], sH2[64][PC], sD1[64][PC], sD2[64][PC], sDY[6][PC];
-    __shared__ float one[PC];
-    const long p0 = (long)blockIdx.x * slice;
-    const long p1 = p0 + slice < M ? p0 + slice : M;
-    // decode owned parameters into (A row, B row) pointers inside the LDS chunk
-    const float *Ar[PPT];
-    const float *Br[PPT];
-    float acc[PPT];
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int j = threadIdx.x + q * MB;
-        acc[q] = 0.f;
-        Ar[q] = one;
-        Br[q] = one;
-        if (j >= NP) continue;
-        if (j < OB1) { Ar[q] = sD1[(j - OW1) / 9]; Br[q] = sX[(j - OW1) % 9]; }
-        else if (j < OW2) { Ar[q] = sD1[j - OB1]; Br[q] = one; }
-        else if (j < OB2) { Ar[q] = sD2[(j - OW2) / 64]; Br[q] = sH1[(j - OW2) % 64]; }
-        else if (j < OW3) { Ar[q] = sD2[j - OB2]; Br[q] = one; }
-        else if (j < OB3) { Ar[q] = sDY[(j - OW3) / 64]; Br[q] = sH2[(j - OW3) % 64]; }
-        else { Ar[q] = sDY[j - OB3]; Br[q] = one; }
-    }
-    for (long c0 = p0; c0 < p1; c0 += PC) {
-        __syncthreads();
-        const int np = (int)(p1 - c0 < PC ? p1 - c0 : PC);
-        for (int e = threadIdx.x; e < 271 * PC; e += MB) {
-            const int row = e / PC, pp = e % PC;
-            const bool ok = pp < np;
-            const long gp = c0 + pp;
-            float v = 0.f;
-            if (row < 9) { if (ok) v = B.X[row * M + gp]; sX[row][pp] = v; }
-            else if (row < 73) { if (ok) v = B.H1[(row - 9) * M + gp]; sH1[row - 9][pp] = v; }
-            else if (row < 137) { if (ok) v = B.H2[(row - 73) * M + gp]; sH2[row - 73][pp] = v; }
-            else if (row < 201) { if (ok) v = B.DA1[(row - 137) * M + gp]; sD1[row - 137][pp] = v; }
-            else if (row < 265) { if (ok) v = B.DA2[(row - 201) * M + gp]; sD2[row - 201][pp] = v; }
-            else { if (ok) v = B.DY[(row - 265) * M + gp]; sDY[row - 265][pp] = v; }
-        }
-        if (threadIdx.x < PC) one[threadIdx.x] = threadIdx.x < np ? 1.f : 0.f;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            float a = 0.f;
-#pragma unroll 8
-            for (int pp = 0; pp < PC; ++pp) a = fmaf(Ar[q][pp], Br[q][pp], a);
-            acc[q] += a;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int j = threadIdx.x + q * MB;
-        if (j < NP) part[(long)blockIdx.x * NP + j] = acc[q];
-    }
-}
-
-// Fixed-order FP64 sum of the slice partials.
-__global__ void k_mlp_bwd_c(const float *__restrict__ part, int nslice, float *__restrict__ grad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < NP) {
-        double a = 0;
-        for (int s = 0; s < nslice; ++s) a += (double)part[(long)s * NP + j];
-        grad[j] = (float)a;
-    }
+// Fixed-order FP64 sum of the workgroups' partials: 64 parameters per workgroup, four
+// interleaved runs over the partials, added in a fixed order.
+__global__ __launch_bounds__(256) void k_mlp_bwd_sum(const float *__restrict__ part, int nslice,
+                                                     float *__restrict__ grad) {
+    __shared__ double sh[4][64];
+    const int jl = threadIdx.x & 63, sg = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + jl;
+    double a = 0;
+    if (j < NP)
+        for (int s = sg; s < nslice; s += 4) a += (double)part[(long)s * NP + j];
+    sh[sg][jl] = a;
+    __syncthreads();
+    if (sg == 0 && j < NP) grad[j] = (float)(((sh[0][jl] + sh[1][jl]) + sh[2][jl]) + sh[3][jl]);
 }
 
 // ---- Adam (Kingma & Ba) ---------------------------------------------------------------------------
@@ -438,44 +587,28 @@ static unsigned ew_blocks(long n) { return (unsigned)std::min<long>(16384, std::
 
 // ---- backward scratch (grow-only, per process) ---------------------------------------------------------
 struct BwdScratch {
-    std::mutex mu;
-    long M = 0;
-    float *buf = nullptr;
     float *part = nullptr;
     double *lpart = nullptr;
     int dev = -1;
 };
 static BwdScratch g_bwd;
+constexpr int BWD_MAXG = 1024;  // at most this many workgroups leave partial sums
 
-static tk_status bwd_scratch(long M, BwdBufs *B, float **part, double **lpart, int nslice, int nblk) {
+static tk_status bwd_scratch(float **part, double **lpart) {
     int dev = 0;
     TK_HIP_CHECK(hipGetDevice(&dev));
-    if (M > g_bwd.M || dev != g_bwd.dev) {
-        if (g_bwd.buf) hipFree(g_bwd.buf);
+    if (!g_bwd.part || dev != g_bwd.dev) {
         if (g_bwd.part) hipFree(g_bwd.part);
         if (g_bwd.lpart) hipFree(g_bwd.lpart);
-        g_bwd.buf = nullptr;
         g_bwd.part = nullptr;
         g_bwd.lpart = nullptr;
-        g_bwd.M = 0;
-        if (hipMalloc((void **)&g_bwd.buf, sizeof(float) * 271 * (size_t)M) != hipSuccess ||
-            hipMalloc((void **)&g_bwd.part, sizeof(float) * (size_t)NP * 1024) != hipSuccess ||
-            hipMalloc((void **)&g_bwd.lpart, sizeof(double) * 4096) != hipSuccess)
+        if (hipMalloc((void **)&g_bwd.part, sizeof(float) * (size_t)NP * BWD_MAXG) != hipSuccess ||
+            hipMalloc((void **)&g_bwd.lpart, sizeof(double) * BWD_MAXG) != hipSuccess)
             return fail(TK_ENOMEM, "network backward scratch allocation failed");
-        g_bwd.M = M;
         g_bwd.dev = dev;
     }
-    float *b = g_bwd.buf;
-    B->X = b;
-    B->H1 = b + 9 * M;
-    B->H2 = b + 73 * M;
-    B->DA1 = b + 137 * M;
-    B->DA2 = b + 201 * M;
-    B->DY = b + 265 * M;
     *part = g_bwd.part;
     *lpart = g_bwd.lpart;
-    (void)nslice;
-    (void)nblk;
     return TK_OK;
 }
 
@@ -499,23 +632,23 @@ tk_status mlp_forward_run(const tk_mlp *w, const float *x9, float *y6, long M, h
 
 static tk_status mlp_backward_run(const tk_mlp *w, const float *x9, const float *t6, const float *dy6, long M,
                                   float *grad, double *loss, hipStream_t s) {
-    BwdBufs B;
     float *part;
     double *lpart;
-    const int nblk_a = (int)std::min<long>(4096, std::max<long>(1, (M + MB - 1) / MB));
-    const int nslice = (int)std::min<long>(1024, std::max<long>(1, (M + 255) / 256));
-    const long slice = (M + nslice - 1) / nslice;
-    TK_TRY(bwd_scratch(M, &B, &part, &lpart, nslice, nblk_a));
-    hipLaunchKernelGGL(k_mlp_bwd_a, dim3(nblk_a), dim3(MB), 0, s, w->w, x9, t6, dy6, M, 1.0f / w->in_scale,
-                       1.0f / w->out_scale, B, lpart);
-    TK_TRY(launch_check("network backward (points)"));
-    hipLaunchKernelGGL(k_mlp_bwd_b, dim3(nslice), dim3(MB), 0, s, B, M, slice, part);
-    TK_TRY(launch_check("network backward (slices)"));
-    hipLaunchKernelGGL(k_mlp_bwd_c, dim3(cdiv(NP, 256)), dim3(256), 0, s, part, nslice, grad);
+    TK_TRY(bwd_scratch(&part, &lpart));
+    // as many workgroups as are resident (each wavefront walks 16-point blocks), no more
+    // than there are blocks
+    const long nblk = (M + 15) / 16;
+    const int G = (int)std::min<long>(std::min<long>(resident_groups(reinterpret_cast<const void *>(&k_mlp_bwd), MB),
+                                                     BWD_MAXG),
+                                      std::max<long>(1, (nblk + MB / 64 - 1) / (MB / 64)));
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(G), dim3(MB), 0, s, w->w, x9, t6, dy6, M, 1.0f / w->in_scale,
+                       1.0f / w->out_scale, part, lpart);
+    TK_TRY(launch_check("network backward"));
+    hipLaunchKernelGGL(k_mlp_bwd_sum, dim3(cdiv(NP, 64)), dim3(256), 0, s, part, G, grad);
     TK_TRY(launch_check("network backward (sum)"));
     if (loss) {
-        std::vector<double> h(nblk_a);
-        TK_HIP_CHECK(hipMemcpyAsync(h.data(), lpart, sizeof(double) * nblk_a, hipMemcpyDeviceToHost, s));
+        std::vector<double> h(G);
+        TK_HIP_CHECK(hipMemcpyAsync(h.data(), lpart, sizeof(double) * G, hipMemcpyDeviceToHost, s));
         TK_HIP_CHECK(hipStreamSynchronize(s));
         double a = 0;
         for (double v : h) a += v;

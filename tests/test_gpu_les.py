@@ -39,7 +39,19 @@ def test_forward_vs_oracle(tk, M):
     assert rel(y, ref) <= 1e-5
 
 
-@pytest.mark.parametrize("M", [300, 65536])
+# flat parameter groups W1, b1, W2, b2, W3, b3
+GROUPS = [(0, 576), (576, 640), (640, 4736), (4736, 4800), (4800, 5184), (5184, 5190)]
+
+
+def assert_grad(g, gref, tol):
+    """Every parameter group on its own (a wrong bias or output-layer entry would hide in
+    the norm of the 4096 hidden weights)."""
+    assert rel(g, gref) <= tol
+    for a, b in GROUPS:
+        assert rel(g[a:b], gref[a:b]) <= tol, (a, b)
+
+
+@pytest.mark.parametrize("M", [1, 17, 300, 65536, 262147])
 def test_loss_and_gradient_vs_oracle(tk, M):
     import torch
     th = theta0(3)
@@ -53,11 +65,14 @@ def test_loss_and_gradient_vs_oracle(tk, M):
     Lref, dy = omlp.mse_loss(y, t.astype(np.float64) / 2.0)
     gref = omlp.backward(th, x.astype(np.float64) / 1.5, dy)
     assert abs(loss - Lref) <= 1e-5 * Lref
-    assert rel(g, gref) <= 1e-4
+    assert_grad(g, gref, 1e-4)
+    # reproducible: the same call gives the same bits
+    net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    assert np.array_equal(net.grad.cpu().numpy(), g)
     # generic backward with a given upstream gradient
     dyr = rng.standard_normal((6, M)).astype(np.float32)
     g2 = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(dyr).cuda()).cpu().numpy()
-    assert rel(g2, omlp.backward(th, x.astype(np.float64) / 1.5, dyr.astype(np.float64))) <= 1e-4
+    assert_grad(g2, omlp.backward(th, x.astype(np.float64) / 1.5, dyr.astype(np.float64)), 1e-4)
 
 
 def test_adam_steps_vs_oracle(tk):
