@@ -170,8 +170,10 @@ def kernel_names(desc, n):
         m = re.search(r"W=(\d+) E=(\d+) v=(\d+)", desc[p])
         if m:
             v = m.group(3)
-            if v in ("1", "2", "3"):  # persistent: <T, L, E, W, MASK>
-                name = "k_strided_pp<float, %d, %s, %s, false>" % (n, m.group(2), m.group(1))
+            if v in ("1", "2", "3", "7", "8", "9"):  # persistent: <T, L, E, W, MASK, WPE>
+                nt = int(m.group(1)) * n // int(m.group(2))
+                wpe = 1 if v in ("1", "2", "3") else 2 * nt // 256
+                name = "k_strided_pp<float, %d, %s, %s, false, %d>" % (n, m.group(2), m.group(1), wpe)
             else:  # one tile per workgroup: <T, L, E, W, MASK, SPLIT>
                 name = "k_strided<float, %d, %s, %s, false, %s>" % (n, m.group(2), m.group(1),
                                                                      "true" if v in ("5", "6") else "false")

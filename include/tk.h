@@ -176,7 +176,8 @@ tk_status fft3d_autotune(int nx, int ny, int nz, int batch, tk_dtype dt, int ite
  * issue the next tile's loads before transforming the current one (1: tiles dealt
  * round-robin, 2: round-robin with a contiguous run per XCD, 3: consecutive tiles per
  * workgroup); 4 = one tile per workgroup, each XCD sweeping its own eighth of the tiles;
- * 5, 6 = 0 and 4 with split exchanges (real, then imaginary parts through half the LDS).
+ * 5, 6 = 0 and 4 with split exchanges (real, then imaginary parts through half the LDS);
+ * 7..9 = 1..3 with the registers held to what two resident workgroups per CU allow.
  * Passes 3, 4, 5 are the solver passes P1 (a = columns), P3 (a = lines per workgroup) and
  * P5 (a = columns) of an L^3 grid (variant 0), pass 6 the solver's Y passes P2 / P4 (a
  * strided tile as for pass 1), pass 7 the time stepper's P5 fused with the next P1 (a =

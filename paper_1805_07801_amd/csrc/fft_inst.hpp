@@ -31,6 +31,15 @@ template <typename T, int L, int CE, int CN> void add_strided(std::vector<Stride
             v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided_pp<T, L, E, W, 2>, 2});
             v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided_pp<T, L, E, W, 3>, 3});
         }
+        // the same with two workgroups per CU: the LDS must hold two tiles and the two
+        // tiles' points must fit in the registers a thread keeps at 2 NT / 256 waves per SIMD
+        if constexpr (sizeof(T) == 4 && NT >= 512 && 2 * strided_lds<T>(L, W) <= 160 * 1024 &&
+                      4 * E <= 512 / (2 * NT / 256) - 40) {
+            constexpr int WPE = 2 * NT / 256;
+            v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided_pp<T, L, E, W, 1, WPE>, 7});
+            v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided_pp<T, L, E, W, 2, WPE>, 8});
+            v.push_back({L, dtype_of<T>(), W, E, NT, strided_lds<T>(L, W), &launch_strided_pp<T, L, E, W, 3, WPE>, 9});
+        }
     }
 }
 

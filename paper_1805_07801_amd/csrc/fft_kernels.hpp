@@ -36,7 +36,8 @@ using StridedFn = void (*)(const StridedArgs &, hipStream_t);
 // var 0: one tile per workgroup, one sweep over the tiles; var 1..3: persistent workgroups
 // with the next tile's loads issued ahead (k_strided_pp), tile order var; var 4: one tile
 // per workgroup, each XCD sweeping its own eighth of the tiles; var 5, 6: as 0 and 4 with
-// split exchanges (real and imaginary parts in turn through half the LDS).
+// split exchanges (real and imaginary parts in turn through half the LDS); var 7..9: as
+// 1..3 with the registers held to what two resident workgroups per CU allow.
 struct StridedKernel {
     int L;
     tk_dtype dt;
@@ -252,8 +253,10 @@ void launch_strided(const StridedArgs &a, hipStream_t s) {
 //   order 2: as 1, with the workgroups numbered XCD by XCD (they are dealt to the 8 XCDs
 //            in turn), so each XCD takes a contiguous run of a round's tiles;
 //   order 3: workgroup g takes the consecutive tiles g q .. g q + q - 1.
-template <typename T, int L, int E, int W, bool MASK>
-__global__ __launch_bounds__(W *(L / E)) void k_strided_pp(const V2<T> *src, V2<T> *dst, long ncols, long CB,
+// WPE: waves per SIMD the register allocation must leave room for (1: no limit; the
+// variants with two resident workgroups per CU ask for 2 NT / 256).
+template <typename T, int L, int E, int W, bool MASK, int WPE>
+__global__ __launch_bounds__(W *(L / E)) __attribute__((amdgpu_waves_per_eu(WPE))) void k_strided_pp(const V2<T> *src, V2<T> *dst, long ncols, long CB,
                                                             long SO, long SI, const V2<T> *__restrict__ twg,
                                                             int inv, T scale, int kl, int ks, long q, int wt,
                                                             int ntail, int order, int rev) {
@@ -299,12 +302,12 @@ __global__ __launch_bounds__(W *(L / E)) void k_strided_pp(const V2<T> *src, V2<
 // Number of workgroups of `kernel` (nt threads) resident on the current device at once.
 int resident_groups(const void *kernel, int nt);
 
-template <typename T, int L, int E, int W, int ORDER>
+template <typename T, int L, int E, int W, int ORDER, int WPE = 1>
 void launch_strided_pp(const StridedArgs &a, hipStream_t s) {
     constexpr int NT = W * (L / E);
     const bool mask = a.kl >= 0 || a.ks >= 0;
-    const void *kp = mask ? reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, true>)
-                          : reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, false>);
+    const void *kp = mask ? reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, true, WPE>)
+                          : reinterpret_cast<const void *>(&k_strided_pp<T, L, E, W, false, WPE>);
     const long G = resident_groups(kp, NT);
     const long q = (a.ncols / W) / G;
     const long left = a.ncols - q * G * W;
@@ -316,11 +319,11 @@ void launch_strided_pp(const StridedArgs &a, hipStream_t s) {
         ntail = (int)((left + wt - 1) / wt);
     }
     if (mask)
-        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, true>), dim3((unsigned)G), dim3(NT), 0, s, (const V2<T> *)a.src,
-                           (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw, a.inv, (T)a.scale, a.kl,
-                           a.ks, q, wt, ntail, ORDER, a.rev);
+        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, true, WPE>), dim3((unsigned)G), dim3(NT), 0, s,
+                           (const V2<T> *)a.src, (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw,
+                           a.inv, (T)a.scale, a.kl, a.ks, q, wt, ntail, ORDER, a.rev);
     else
-        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, false>), dim3((unsigned)G), dim3(NT), 0, s,
+        hipLaunchKernelGGL((k_strided_pp<T, L, E, W, false, WPE>), dim3((unsigned)G), dim3(NT), 0, s,
                            (const V2<T> *)a.src, (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI, (const V2<T> *)a.tw,
                            a.inv, (T)a.scale, a.kl, a.ks, q, wt, ntail, ORDER, a.rev);
 }
