@@ -220,10 +220,21 @@ const std::vector<ZR2RKernel> &z_r2r_kernels() {
     return K;
 }
 
+// Tile of the strided sine / cosine kernel: at least 16 columns, so that every row access
+// is a whole 128-byte line in FP32 (8-column tiles fetched each line in two halves at
+// different times), within 1024 threads and the LDS; small lengths keep 512-thread tiles.
+template <typename T> constexpr int r2r_E(int L) { return L / default_E(L) > 64 ? 2 * default_E(L) : default_E(L); }
+template <typename T> constexpr int r2r_W(int L) {
+    const int E = r2r_E<T>(L), tpl = L / E;
+    int W = 512 / tpl > 16 ? 512 / tpl : 16;
+    while (W > 1 && (W * tpl > 1024 || (L * (W + 1) + 2 * L) * 2 * (int)sizeof(T) > 160 * 1024)) W /= 2;
+    return W;
+}
+
 template <typename T, int L> void add_r2r(std::vector<R2RKernel> &v) {
-    constexpr int E = default_E(L);
-    constexpr int W = (512 * E / L) > 0 ? 512 * E / L : 1;
-    static_assert(W * (L / E) == 512 || L / E > 512, "tile shape");
+    constexpr int E = r2r_E<T>(L);
+    constexpr int W = r2r_W<T>(L);
+    static_assert(rplan_ok(L, E) && W >= 1 && W * (L / E) <= 1024, "tile shape");
     v.push_back({L, sizeof(T) == 4 ? TK_F32 : TK_F64, W, E, [](const R2RArgs &a, hipStream_t s) {
                      hipLaunchKernelGGL((k_r2r<T, L, E, W>), dim3(cdiv(a.ncols, W)), dim3(W * (L / E)), 0, s,
                                         (const V2<T> *)a.src, (V2<T> *)a.dst, a.ncols, a.CB, a.SO, a.SI,

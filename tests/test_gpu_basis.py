@@ -9,7 +9,9 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("shape,bx,by", [((16, 24, 8), 1, 0), ((32, 16, 12), 2, 0), ((12, 32, 16), 0, 1),
-                                         ((24, 8, 8), 2, 2), ((64, 48, 16), 1, 2), ((8, 96, 8), 2, 1)])
+                                         ((24, 8, 8), 2, 2), ((64, 48, 16), 1, 2), ((8, 96, 8), 2, 1),
+                                         ((192, 8, 8), 1, 0), ((8, 256, 8), 0, 2), ((384, 12, 8), 2, 1),
+                                         ((8, 768, 8), 1, 2), ((1024, 8, 8), 1, 2), ((8, 1024, 8), 2, 1)])
 def test_basis_vs_oracle(tk, shape, bx, by, dt):
     import torch
     tdt = torch.float32 if dt == "f32" else torch.float64
