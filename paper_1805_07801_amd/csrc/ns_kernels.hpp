@@ -735,8 +735,9 @@ template <typename C> __global__ void k_zero(C *p, long n) {
 // columns (16 for FP32, 8 for FP64, fewer if the workgroup would exceed its thread cap).
 // They hold three fields per thread; a 1024-thread workgroup (4 waves per SIMD) leaves 128
 // registers per thread, enough at E <= 8 in FP32 (about 112), so the cap is 1024 threads
-// there and 512 otherwise.  The convection passes hold a fourth field and keep 512
-// (ns_rbc_W).  P3 uses E = default_E(N/2) and 256 threads.
+// there and 512 otherwise.  The convection passes hold a fourth field and still fit
+// (ns_rbc_W: 123 and 128 registers for its P1 and P5 at 512^3 in FP32; with 8-column tiles
+// each 128-byte line was fetched in two halves).  P3 uses E = default_E(N/2) and 256 threads.
 template <typename T> constexpr int ns_x_E(int N) { return default_E(N); }
 template <typename T> constexpr int ns_x_cap(int N) { return (sizeof(T) == 4 && ns_x_E<T>(N) <= 8) ? 1024 : 512; }
 template <typename T> constexpr int ns_x_W(int N) {
@@ -746,11 +747,7 @@ template <typename T> constexpr int ns_x_W(int N) {
     while (W * (N / E) < 64) W *= 2;
     return W;
 }
-template <typename T> constexpr int ns_rbc_W(int N) {
-    int W = ns_x_W<T>(N);
-    while (W > 1 && W * (N / ns_x_E<T>(N)) > 512) W /= 2;
-    return W;
-}
+template <typename T> constexpr int ns_rbc_W(int N) { return ns_x_W<T>(N); }
 constexpr int ns_z_LPW(int N) {
     int L = N / 2, E = default_E(L), TPL = L / E;
     return TPL >= 256 ? 1 : 256 / TPL;
