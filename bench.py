@@ -345,6 +345,19 @@ if leg.startswith("pair"):
     t = time.perf_counter()
     g = offt.irfft3(offt.rfft3(f))
     out["s"] = time.perf_counter() - t
+elif leg == "scipy512":
+    # library context, not the oracle: scipy's pocketfft on all logical CPUs, FP64 and FP32
+    import os
+    import scipy.fft as sf
+    w = os.cpu_count() or 1
+    out["threads"] = w
+    f = synth.gaussian_field((512, 512, 512), 0)
+    for key, dt in (("s", np.float64), ("s_fp32", np.float32)):
+        x = f.astype(dt)
+        t = time.perf_counter()
+        g = sf.irfftn(sf.rfftn(x, workers=w), s=x.shape, workers=w)
+        out[key] = time.perf_counter() - t
+        del x, g
 elif leg == "ns32":
     u = offt.rfft3(synth.taylor_green(32))
     t = time.perf_counter()
@@ -367,14 +380,16 @@ print(json.dumps(out))
 def cpu_legs():
     """The oracle on the rest of the workloads, each in a child process: one 512^3 pair on
     one thread, one 1024^3 pair, and one IF-RK2 step of the 32^3 FP64 Taylor-Green case
-    (repeated for 2 s) and of the 512^3 decaying-turbulence field, on all threads."""
+    (repeated for 2 s) and of the 512^3 decaying-turbulence field, on all threads; and, as
+    library context only, scipy.fft's 512^3 pair in FP64 and FP32."""
     import subprocess
     here = os.path.dirname(os.path.abspath(__file__))
     R, C = field_bytes(512)
     R2, C2 = field_bytes(1024)
     legs = {}
     for name, leg, env in (("pair512_1thread", "pair512", {"OMP_NUM_THREADS": "1"}), ("pair1024", "pair1024", {}),
-                           ("ns32_fp64_step", "ns32", {}), ("ns512_step", "ns512", {})):
+                           ("ns32_fp64_step", "ns32", {}), ("ns512_step", "ns512", {}),
+                           ("scipy_pair512_library_context", "scipy512", {})):
         e = dict(os.environ)
         e.update(env)
         try:
@@ -387,6 +402,9 @@ def cpu_legs():
         rec = {"s": round(d["s"], 4), "threads": d["threads"]}
         if leg == "pair512":
             rec["GBps"] = round((2 * R + 10 * C) / d["s"] / 1e9, 3)
+        elif leg == "scipy512":
+            rec["kind"] = "library (scipy.fft), not the oracle"
+            rec["s_fp32"] = round(d["s_fp32"], 4)
         elif leg == "pair1024":
             rec["GBps"] = round((2 * R2 + 10 * C2) / d["s"] / 1e9, 3)
         else:
