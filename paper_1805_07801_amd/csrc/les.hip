@@ -7,6 +7,7 @@
 // FP32.  Flat parameter order W1[64][9], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "ns_api.hpp"
@@ -451,19 +452,24 @@ __global__ __launch_bounds__(MB) void k_mlp_bwd(const uint16_t *__restrict__ wb,
     }
 }
 
-// Fixed-order FP64 sum of the workgroups' partials: 64 parameters per workgroup, four
+// Fixed-order FP64 sum of the workgroups' partials: 16 parameters per workgroup, sixteen
 // interleaved runs over the partials, added in a fixed order.
-__global__ __launch_bounds__(256) void k_mlp_bwd_sum(const float *__restrict__ part, int nslice,
-                                                     float *__restrict__ grad) {
-    __shared__ double sh[4][64];
-    const int jl = threadIdx.x & 63, sg = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + jl;
+constexpr int SUM_J = 16, SUM_G = 16;
+__global__ __launch_bounds__(SUM_J * SUM_G) void k_mlp_bwd_sum(const float *__restrict__ part, int nslice,
+                                                               float *__restrict__ grad) {
+    __shared__ double sh[SUM_G][SUM_J];
+    const int jl = threadIdx.x % SUM_J, sg = threadIdx.x / SUM_J;
+    const int j = blockIdx.x * SUM_J + jl;
     double a = 0;
     if (j < NP)
-        for (int s = sg; s < nslice; s += 4) a += (double)part[(long)s * NP + j];
+        for (int s = sg; s < nslice; s += SUM_G) a += (double)part[(long)s * NP + j];
     sh[sg][jl] = a;
     __syncthreads();
-    if (sg == 0 && j < NP) grad[j] = (float)(((sh[0][jl] + sh[1][jl]) + sh[2][jl]) + sh[3][jl]);
+    if (sg == 0 && j < NP) {
+        double r = sh[0][jl];
+        for (int g = 1; g < SUM_G; ++g) r += sh[g][jl];
+        grad[j] = (float)r;
+    }
 }
 
 // ---- Adam (Kingma & Ba) ---------------------------------------------------------------------------
@@ -587,6 +593,7 @@ static unsigned ew_blocks(long n) { return (unsigned)std::min<long>(16384, std::
 
 // ---- backward scratch (grow-only, per process) ---------------------------------------------------------
 struct BwdScratch {
+    std::mutex mu;  // guards the allocation; the buffers themselves are shared (see tk.h)
     float *part = nullptr;
     double *lpart = nullptr;
     int dev = -1;
@@ -597,6 +604,7 @@ constexpr int BWD_MAXG = 1024;  // at most this many workgroups leave partial su
 static tk_status bwd_scratch(float **part, double **lpart) {
     int dev = 0;
     TK_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_bwd.mu);
     if (!g_bwd.part || dev != g_bwd.dev) {
         if (g_bwd.part) hipFree(g_bwd.part);
         if (g_bwd.lpart) hipFree(g_bwd.lpart);
@@ -644,7 +652,7 @@ static tk_status mlp_backward_run(const tk_mlp *w, const float *x9, const float 
     hipLaunchKernelGGL(k_mlp_bwd, dim3(G), dim3(MB), 0, s, w->w, x9, t6, dy6, M, 1.0f / w->in_scale,
                        1.0f / w->out_scale, part, lpart);
     TK_TRY(launch_check("network backward"));
-    hipLaunchKernelGGL(k_mlp_bwd_sum, dim3(cdiv(NP, 64)), dim3(256), 0, s, part, G, grad);
+    hipLaunchKernelGGL(k_mlp_bwd_sum, dim3(cdiv(NP, SUM_J)), dim3(SUM_J * SUM_G), 0, s, part, G, grad);
     TK_TRY(launch_check("network backward (sum)"));
     if (loss) {
         std::vector<double> h(G);
