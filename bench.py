@@ -269,11 +269,26 @@ def traffic_from_profile(kernel_name):
 VALU_PEAK_GIPS = 256 * 4 * 2.4 / 4
 
 
+def p3_kernel_name(n=512):
+    """Template name of the solver's fused Z pass at n^3 FP32 under the committed tile cache
+    (tile-table pass 4: a = lines per workgroup, E = points per thread; default 8 and 8)."""
+    from paper_1805_07801_amd import tune
+    a, E = 8, 8
+    if os.path.exists(tune.DEFAULT_CACHE):
+        with open(tune.DEFAULT_CACHE) as fh:
+            for line in fh:
+                if line.strip():
+                    e = json.loads(line)
+                    if e["L"] == n and e["dtype"] == 0 and e["pass"] == 4:
+                        a, E = e["a"], e["E"]
+    return "k_ns_p3<float, %d, %d, %d, false>" % (n // 2, E, a)
+
+
 def p3_alu_roofline(ms):
     """ALU roofline of the fused Z pass of the 512^3 solver (six inverse and three forward
     line transforms with the products between them, bound by vector ALU issue): VALU
     instructions per launch from the committed counter summary / the live mean launch time."""
-    name = "k_ns_p3<float, 256, 8, 8, false>"
+    name = p3_kernel_name(512)
     n_inst = profile_record("ns512_counters.txt", ("fft_core.hpp", "ns_kernels.hpp"),
                             "valu_instructions_per_launch", name)
     if n_inst is None:
