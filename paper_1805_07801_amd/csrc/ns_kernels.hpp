@@ -284,10 +284,17 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = nx[i];
         if (f + 1 < NIN) load(nx, f + 1);
-        // X[L - k] from the mirror lane (X[L] itself is a masked mode: zero)
+        // X[L - k] from the mirror lane (X[L] itself is a masked mode: zero).  Register r
+        // holds X[jt + r TPL]; it is zero on every lane when r TPL >= KZC0, so register i
+        // of the merge has X[k] = 0 when i is such a register, and X[L - k] = 0 when its
+        // mirror E - 1 - i is one (for lane 0, whose mirror register is E - i, as well;
+        // lane 0's register 0 is the k = 0 case, which takes no mirror).  Those terms are
+        // left out at compile time, and so are the shuffles that would fetch zeros.
         mirror<T, L, E>(v, xm, jt);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
+            const bool xk_zero = i * TPL >= KZC0;
+            const bool xc_zero = (E - 1 - i) * TPL >= KZC0;
             // k = jt + i TPL is 0 only in register 0 of lane 0 of the line
             const bool k0 = i == 0 && jt == 0;
             C xk = v[i];
@@ -296,8 +303,18 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
                 xc = k0 ? mk<T>(0, 0) : xc;
                 xk.y = k0 ? (T)0 : xk.y;
             }
-            const C a = cadd(xk, xc);
-            const C b = cmul(cconj(split_tw(i)), csub(xk, xc));
+            C a, d;
+            if (xk_zero) {
+                a = xc;
+                d = mk<T>(-xc.x, -xc.y);
+            } else if (xc_zero) {
+                a = xk;
+                d = xk;
+            } else {
+                a = cadd(xk, xc);
+                d = csub(xk, xc);
+            }
+            const C b = cmul(cconj(split_tw(i)), d);
             v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
         }
         xform(v);
