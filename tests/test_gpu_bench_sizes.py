@@ -1,6 +1,7 @@
 """Oracle parity at the sizes the benchmark times: the 1024^3 transform pair with the tuned
 tiles and the pair's plan flags, IF-RK4 and Rayleigh-Benard steps at 512^3, the sine-basis
-(SFF) transform at 512^3 and the energy transfer at 256^3.
+(SFF) transform at 512^3 and the energy transfer at 256^3; and the solver at its largest
+grid, 1024^3, on a band-limited field whose exact spectra the oracle gives on a small grid.
 
 Grids too large for the full oracle transform are checked on complete kz-planes, complete
 x-lines, or through separable fields whose exact spectrum is a product of 1D transforms."""
@@ -228,3 +229,47 @@ def test_energy_transfer_256(tk):
     assert np.max(np.abs(got - ref)) <= 1e-5 * scale
     assert abs(np.sum(got)) <= 1e-5 * scale * len(got)
     s.close()
+
+
+def _embed(small, n):
+    """A band-limited spectral state on the n^3 grid from its modes on a small grid (oracle
+    layout [c][m][m][m/2+1], every nonzero mode with |k_i| < m/2): (indices, values) of the
+    nonzero modes at their places on the n^3 grid."""
+    m = small.shape[1]
+    c, i, j, l = np.nonzero(np.abs(small) > 1e-14 * np.max(np.abs(small)))
+    wrap = lambda a: np.where(a < m // 2, a, a - m) % n
+    return (c, wrap(i), wrap(j), l), small[c, i, j, l]
+
+
+def test_ns_1024_taylor_green_rhs_and_step(tk):
+    """The solver at its largest grid, 1024^3 FP32 with the fused stepper: the right-hand
+    side of the Taylor-Green field and one IF-RK2 step against the oracle.  Taylor-Green
+    holds modes |k_i| <= 1, its right-hand side |k_i| <= 2 and one step's second stage
+    |k_i| <= 4, all inside the 2/3 set of a 16^3 grid, so the oracle's 16^3 results are the
+    exact 1024^3 spectra; every other mode of the 1024^3 results must stay zero."""
+    import torch
+    n, m = 1024, 16
+    nu, h = 0.01, 0.01
+    u16 = offt.rfft3(synth.taylor_green(m))
+    r16 = ons.rhs(u16)
+    s16 = ons.ifrk2_step(u16, nu, h)[0]
+    _say("1024^3 Taylor-Green right-hand side and step")
+    s = tk.NS(n, dtype=torch.float32, nu=nu)
+    try:
+        (c, i, j, l), v = _embed(u16, n)
+        u = torch.zeros((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+        at = lambda a: torch.from_numpy(a.astype(np.int64)).cuda()
+        u[at(c), at(i), at(j), at(l)] = torch.from_numpy(v.astype(np.complex64)).cuda()
+        for ref, got_fn in ((r16, lambda: s.rhs(u)), (s16, lambda: (s.step(u, h, 1), u)[1])):
+            got = got_fn()
+            (rc, ri, rj, rl), rv = _embed(ref, n)
+            g = got[at(rc), at(ri), at(rj), at(rl)].cpu().numpy().astype(np.complex128)
+            rn = np.linalg.norm(rv)
+            assert np.linalg.norm(g - rv) <= 1e-5 * rn
+            # the rest of the 1024^3 spectrum (the reference's modes cleared) stays zero
+            got[at(rc), at(ri), at(rj), at(rl)] = 0
+            rest = float(torch.linalg.vector_norm(got))
+            assert rest <= 1e-5 * rn, rest / rn
+            del got
+    finally:
+        s.close()
