@@ -514,7 +514,8 @@ def extension_rates(tk, torch, n=512):
     """The rows built beyond the hot path, each at 512^3 FP32: IF-RK4 steps/s of the
     decaying-turbulence field (CFL 0.5), the energy-transfer diagnostics, Rayleigh-Benard
     (FFF) IF-RK2 steps/s with the GB/s of each of its passes, and the sine-basis (SFF) and
-    all-sine/cosine (SSS) transform pairs with the GB/s of each pass, HIP events throughout."""
+    all-sine/cosine (SSS) transform pairs with the GB/s of each pass; and the IF-RK2 solver
+    at 1024^3, HIP events throughout."""
     import synth
     out = {}
     R, C = field_bytes(n)
@@ -580,6 +581,25 @@ def extension_rates(tk, torch, n=512):
         plan.close()
         del X, y
     del x
+    torch.cuda.empty_cache()
+    # the solver at its largest grid: 1024^3 IF-RK2 (CFL 0.5) of a random solenoidal field
+    # (noise drawn on the device; the 15 fields of the solver take 65 GB of the 288 GB)
+    m = 1024
+    noise = torch.randn((3, m, m, m), generator=g, device="cuda", dtype=torch.float32)
+    ns = tk.NS(m, dtype=torch.float32, nu=5e-4, cfl=0.5)
+    u = ns.init_random(noise)
+    del noise
+    ns.step(u, 0.0, 2)
+    k = 10
+    ms = event_time(torch, lambda: ns.step(u, 0.0, k), 1) / k
+    pb = ns_pass_bytes(m)
+    step_bytes = 2 * sum(sum(pb[p]) for p in ("P2", "P3", "P4", "P5+P1"))
+    out["ns1024_rk2"] = {"steps_per_s": round(1e3 / ms, 2), "ms_per_step": round(ms, 3),
+                         "alg_GB_per_step": round(step_bytes / 1e9, 2),
+                         "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                         "frac_hbm_peak": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 3)}
+    ns.close()
+    del u
     torch.cuda.empty_cache()
     return out
 
