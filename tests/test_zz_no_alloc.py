@@ -1,6 +1,7 @@
 """The allocation-free c2r entry point (static device scratch as its workspace) against
 the allocating one, through the C ABI: two calls in a row, the second on a smaller grid,
-bit-identical to fft3d_c2r (same kernels) and within the FFT tolerance of the oracle."""
+bit-identical to fft3d_c2r (same kernels) and within the FFT tolerance of the oracle; and
+captured in a HIP graph, as the callers it is for use it."""
 import ctypes
 
 import numpy as np
@@ -58,4 +59,34 @@ def test_noalloc_c2r_rejects_a_workspace_beyond_the_scratch(tk):
     plan.c2r_noalloc(X, y)
     torch.cuda.synchronize()
     assert diag.rel_l2(y.cpu().numpy(), f) <= 1e-5
+    plan.close()
+
+
+def test_noalloc_c2r_under_graph_capture(tk):
+    """The callers this entry point is for: a HIP graph captured around it (and the r2c that
+    feeds it), replayed several times with eager work and synchronisation between the
+    replays; every replay equals the eager result bit for bit."""
+    import torch
+    n = 128
+    print("no-alloc c2r under graph capture n=%d" % n, flush=True)
+    plan = tk.FFT3D(n, dtype=torch.float32)
+    x = torch.from_numpy(synth.gaussian_field((1, n, n, n), 34)).cuda()
+    X = plan.empty_cplx()
+    y = plan.empty_real()
+    plan.r2c(x, X)
+    plan.c2r_noalloc(X, y)  # eager: kernels loaded and the scratch address taken before capture
+    torch.cuda.synchronize()
+    ref = y.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.r2c(x, X)
+        plan.c2r_noalloc(X, y)
+    for k in range(3):
+        y.fill_(float("nan"))
+        X.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), k
+    assert diag.rel_l2(y.cpu().numpy(), x.cpu().numpy()) <= 1e-5
     plan.close()
