@@ -455,14 +455,14 @@ __global__ __launch_bounds__(MB) void k_mlp_bwd(const uint16_t *__restrict__ wb,
 // Fixed-order FP64 sum of the workgroups' partials: 16 parameters per workgroup, sixteen
 // interleaved runs over the partials, added in a fixed order.
 constexpr int SUM_J = 16, SUM_G = 16;
-__global__ __launch_bounds__(SUM_J * SUM_G) void k_mlp_bwd_sum(const float *__restrict__ part, int nslice,
+__global__ __launch_bounds__(SUM_J * SUM_G) void k_mlp_bwd_sum(const float *__restrict__ part, int npart,
                                                                float *__restrict__ grad) {
     __shared__ double sh[SUM_G][SUM_J];
     const int jl = threadIdx.x % SUM_J, sg = threadIdx.x / SUM_J;
     const int j = blockIdx.x * SUM_J + jl;
     double a = 0;
     if (j < NP)
-        for (int s = sg; s < nslice; s += SUM_G) a += (double)part[(long)s * NP + j];
+        for (int s = sg; s < npart; s += SUM_G) a += (double)part[(long)s * NP + j];
     sh[sg][jl] = a;
     __syncthreads();
     if (sg == 0 && j < NP) {
