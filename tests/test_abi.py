@@ -73,3 +73,38 @@ def test_plan_rejects_unknown_and_conflicting_flags(lib):
     both = tk.TK_FFT_C2R_Y_FIRST | tk.TK_FFT_C2R_OVERWRITE
     assert lib.fft3d_plan_create(ctypes.byref(h), 16, 16, 16, 1, tk.TK_F32, both) == tk.TK_EINVAL
     assert h.value is None
+
+
+def test_newer_entry_points_reject_bad_arguments(lib):
+    """Argument checks that come before any device call: the allocation-free inverse, the
+    convection solver, ensembles, the closure network, Adam and the LES step."""
+    import paper_1805_07801_amd as tk
+    assert lib.fft3d_c2r_noalloc(None, None, None, None) == tk.TK_EINVAL
+    assert lib.rbc_step(None, None, 0.1, 1, None, None) == tk.TK_EINVAL
+    assert lib.rbc_destroy(None) == tk.TK_OK
+    assert lib.ns_batch_step(None, None, 0.1, 1, None, None) == tk.TK_EINVAL
+    assert lib.ns_batch_destroy(None) == tk.TK_OK
+    assert lib.sgs_mlp_forward(None, None, None, 1, None) == tk.TK_EINVAL
+    assert lib.sgs_adam_step(None, None, None, None) == tk.TK_EINVAL
+    w = tk.TkMlp()  # NULL weights
+    assert lib.sgs_mlp_forward(ctypes.byref(w), None, None, 1, None) == tk.TK_EINVAL
+    assert lib.les_step(None, None, None, 0.1, 1, None, None, None) == tk.TK_EINVAL
+
+
+def test_tile_table_on_the_host(lib):
+    """The tile registry answers without a device: every candidate of a pass can be set, the
+    persistent strided variants with one and with two workgroups per CU are among the
+    512-point ones, and a tile that is not compiled is refused."""
+    import paper_1805_07801_amd as tk
+    n = lib.fft3d_tile_candidates(512, tk.TK_F32, 1, None, None, None, 0)
+    assert n > 10
+    a, e, v = (ctypes.c_int * n)(), (ctypes.c_int * n)(), (ctypes.c_int * n)()
+    assert lib.fft3d_tile_candidates(512, tk.TK_F32, 1, a, e, v, n) == n
+    variants = set(v)
+    assert {0, 2, 4, 6, 8} <= variants
+    try:
+        for i in range(n):
+            assert lib.fft3d_tune_set(512, tk.TK_F32, 1, a[i], e[i], v[i]) == tk.TK_OK
+        assert lib.fft3d_tune_set(512, tk.TK_F32, 1, 3, 8, 0) == tk.TK_EUNSUPPORTED
+    finally:
+        lib.fft3d_tune_clear()
