@@ -95,14 +95,15 @@ def test_every_tile_candidate_matches_oracle(tk, n):
         tk.tune_clear()
 
 
-@pytest.mark.parametrize("L", [256, 512])
+@pytest.mark.parametrize("L", [256, 512, 1024])
 def test_persistent_candidates_full_rounds_and_tail(tk, L):
     """The persistent strided variants (all three tile orders, with one or two workgroups
-    per CU) at sizes where every workgroup takes several full tiles and the leftover
-    columns are cut into narrow tail tiles (ncols = 256 * 65)."""
+    per CU) at sizes where every workgroup takes one or more full tiles and the leftover
+    columns are cut into narrow tail tiles (ncols = 256 * 65, or 64 * 65 at 1024 points)."""
     import torch
+    m = 256 if L < 1024 else 64
     try:
-        for p, shape in ((1, (256, L, 128)), (2, (L, 256, 128))):
+        for p, shape in ((1, (m, L, 128)), (2, (L, m, 128))):
             f = synth.gaussian_field((1,) + shape, 7 + p)
             ref = offt.rfft3(f[0].astype(np.float64))
             cands = [c for c in tk.tile_candidates(L, torch.float32, p) if c[2] in (1, 2, 3, 7, 8, 9)]
