@@ -30,21 +30,30 @@ __device__ __forceinline__ uint16_t f32_bf16(float f) {
 //   erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x).
 // Branch-free (one reciprocal, one exponential), where the library erf takes two
 // divergent ranges: the network's activations are its main vector-ALU cost.
-__device__ __forceinline__ float erf_as(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-    float q = fmaf(1.061405429f, t, -1.453152027f);
-    q = fmaf(q, t, 1.421413741f);
-    q = fmaf(q, t, -0.284496736f);
-    q = fmaf(q, t, 0.254829592f);
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * ax * ax);  // exp(-x^2)
-    return copysignf(fmaf(-q * t, e, 1.0f), x);
+// The GELU needs it at x / sqrt 2, through the normal tail Phi(-|x|) = erfc(|x| / sqrt 2) / 2:
+// tail = t P(t) e / 2 with t = 1 / (1 + p |x| / sqrt 2) and e = exp(-x^2 / 2), the 1/2 and
+// the 1/sqrt 2 folded into the constants.
+__device__ __forceinline__ float normal_tail(float x, float &e) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(x), 1.0f));
+    float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    q = fmaf(q, t, 0.5f * 1.421413741f);
+    q = fmaf(q, t, 0.5f * -0.284496736f);
+    q = fmaf(q, t, 0.5f * 0.254829592f);
+    e = __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x);  // exp(-x^2 / 2)
+    return q * t * e;
 }
-// GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2 and its derivative Phi(x) + x phi(x).
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) = max(x, 0) - |x| Phi(-|x|): the small negative branch comes out of the
+// tail directly instead of as the difference of two numbers near 1.
+__device__ __forceinline__ float gelu(float x) {
+    float e;
+    const float tail = normal_tail(x, e);
+    return fmaf(-fabsf(x), tail, fmaxf(x, 0.0f));
+}
+// GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi) with the tail's exponential.
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
-           x * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x) * 0.39894228040143268f;
+    float e;
+    const float tail = normal_tail(x, e);
+    return (x >= 0.0f ? 1.0f - tail : tail) + x * e * 0.39894228040143268f;
 }
 
 // ---- forward ------------------------------------------------------------------------------------------
@@ -56,22 +65,63 @@ __device__ __forceinline__ void load_weights(float *w, const uint16_t *__restric
 
 // Forward on the matrix cores.  Each layer is a product D = W H of the weights (outputs x
 // inputs) and the activations (inputs x points), taken 16 points at a time by one
-// wavefront with v_mfma_f32_16x16x4_f32 (FP32 operands and accumulation: the products and
-// sums are the FP32 ones of the definition, in another order).  Operand layouts of that
-// instruction on a wavefront, lane l = 16 kk + c (kk < 4, c < 16):
-//   A (16 x 4): lane l holds A[c][kk];  B (4 x 16): B[kk][c];
-//   D (16 x 16): 4 values, D[4 kk + r][c], r < 4.
-// So a lane holds, for point c of the block, outputs 4 kk + r of each 16-row tile q:
-// feature o = 16 q + 4 kk + r.  The next layer consumes them in place: its step (q, r)
-// takes from lane l the K slot kk = feature 16 q + 4 kk + r, and its A operand is the
-// weight column of that same feature, so activations never leave the registers.  The
-// weights (up to 64 per lane for W2) and biases are per-lane constants, loaded once per
+// wavefront with v_mfma_f32_16x16x32_bf16.  The weights are BF16 parameters already; each
+// FP32 activation is split exactly into three BF16 terms, h = hi + mid + lo (split3), so
+// every product w h_i is exact in FP32 and the sums run in FP32 on the FP32 accumulators:
+// the FP32 arithmetic of the definition, in another order, at a quarter of the matrix
+// cycles of the FP32 instruction.  Operand layouts on a wavefront, lane l = 16 kk + c
+// (kk < 4, c < 16):
+//   A (16 x 32): lane l holds 8 values of row c (its K slots);  B (32 x 16): the same K
+//   slots of column c;  D (16 x 16): 4 values, D[4 kk + r][c], r < 4.
+// Which K slot carries which input feature is free (the sum is order-free) as long as A
+// and B agree, so a lane holds, for point c of the block, outputs 4 kk + r of each 16-row
+// tile q (feature o = 16 q + 4 kk + r) and the next layer consumes them in place: K step s
+// takes from lane l its outputs of tiles 2 s and 2 s + 1, slot j = 4 (q - 2 s) + r, and its A
+// operand is the weight column of that same feature.  The 9 inputs take slots j < 3 of
+// lanes kk < 3 (feature 3 kk + j).  The weights are per-lane constants, loaded once per
 // wavefront; wavefronts walk the 16-point blocks.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int MB = 256;
 
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma32(v4u a, v4u b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
+// Two BF16 bit patterns in one register, element 2 p in the low half.
+__device__ __forceinline__ unsigned pack_hi16(unsigned lo_elem, unsigned hi_elem) {
+    return (lo_elem >> 16) | (hi_elem & 0xffff0000u);
+}
+// v[j] = hi[j] + mid[j] + lo[j] exactly: truncating an FP32 value to its BF16 head leaves a
+// remainder of at most 16 significant bits, and truncating that one leaves at most 8, which
+// BF16 holds exactly.
+__device__ __forceinline__ void split3(const float (&v)[8], v4u &hi, v4u &mid, v4u &lo) {
+    unsigned uh[8], um[8], ul[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        uh[j] = __float_as_uint(v[j]);
+        const float r1 = v[j] - __uint_as_float(uh[j] & 0xffff0000u);
+        um[j] = __float_as_uint(r1);
+        ul[j] = __float_as_uint(r1 - __uint_as_float(um[j] & 0xffff0000u));
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        hi[p] = pack_hi16(uh[2 * p], uh[2 * p + 1]);
+        mid[p] = pack_hi16(um[2 * p], um[2 * p + 1]);
+        lo[p] = pack_hi16(ul[2 * p], ul[2 * p + 1]);
+    }
+}
+// D += A (hi + mid + lo), the smallest terms first
+__device__ __forceinline__ v4f mfma32x3(v4u a, const float (&v)[8], v4f d) {
+    v4u hi, mid, lo;
+    split3(v, hi, mid, lo);
+    d = mfma32(a, lo, d);
+    d = mfma32(a, mid, d);
+    return mfma32(a, hi, d);
 }
 
 __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb, const float *__restrict__ x9,
@@ -79,26 +129,39 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
     const int lane = threadIdx.x & 63;
     const int kk = lane >> 4, c = lane & 15;
     auto w = [&](int i) { return bf16_f32(wb[i]); };
-    float a1[4][3], a2[4][16], a3[16];
+    auto bits = [&](bool ok, int i) { return ok ? (unsigned)wb[i] << 16 : 0u; };
+    // A operands as BF16 pairs: layer 1 [q], layer 2 [q][s], layer 3 [s]
+    v4u a1[4], a2[4][2], a3[2];
     v4f b1[4], b2[4], b3;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int t = 0; t < 3; ++t) a1[q][t] = (4 * t + kk < 9) ? w(OW1 + (16 * q + c) * 9 + 4 * t + kk) : 0.f;
+        for (int p = 0; p < 4; ++p) {
+            const int j0 = 2 * p, j1 = 2 * p + 1, f0 = 3 * kk + j0, f1 = 3 * kk + j1;
+            a1[q][p] = pack_hi16(bits(j0 < 3 && f0 < 9, OW1 + (16 * q + c) * 9 + f0),
+                                 bits(j1 < 3 && f1 < 9, OW1 + (16 * q + c) * 9 + f1));
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int n0 = 16 * (2 * s + (2 * p >> 2)) + 4 * kk + (2 * p & 3);
+                a2[q][s][p] = pack_hi16(bits(true, OW2 + (16 * q + c) * 64 + n0),
+                                        bits(true, OW2 + (16 * q + c) * 64 + n0 + 1));
+            }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             b1[q][r] = w(OB1 + 16 * q + 4 * kk + r);
             b2[q][r] = w(OB2 + 16 * q + 4 * kk + r);
         }
-#pragma unroll
-        for (int qi = 0; qi < 4; ++qi)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a2[q][4 * qi + r] = w(OW2 + (16 * q + c) * 64 + 16 * qi + 4 * kk + r);
     }
 #pragma unroll
-    for (int qi = 0; qi < 4; ++qi)
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a3[4 * qi + r] = c < 6 ? w(OW3 + c * 64 + 16 * qi + 4 * kk + r) : 0.f;
+        for (int p = 0; p < 4; ++p) {
+            const int n0 = 16 * (2 * s + (2 * p >> 2)) + 4 * kk + (2 * p & 3);
+            a3[s][p] = pack_hi16(bits(c < 6, OW3 + c * 64 + n0), bits(c < 6, OW3 + c * 64 + n0 + 1));
+        }
 #pragma unroll
     for (int r = 0; r < 4; ++r) b3[r] = (4 * kk + r < 6) ? w(OB3 + 4 * kk + r) : 0.f;
 
@@ -108,46 +171,51 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
     auto load_x = [&](long blk, float (&xv)[3]) {
         const long p = blk * 16 + c;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int f = 4 * t + kk;
-            xv[t] = (blk < nblk && p < M && f < 9) ? x9[f * M + p] * in_inv : 0.f;
+        for (int j = 0; j < 3; ++j) {
+            const int f = 3 * kk + j;
+            xv[j] = (blk < nblk && p < M && f < 9) ? x9[f * M + p] * in_inv : 0.f;
         }
     };
     float xn[3];
     load_x(wv, xn);
     for (long blk = wv; blk < nblk; blk += nwv) {
-        float xv[3] = {xn[0], xn[1], xn[2]};
+        const float xv[8] = {xn[0], xn[1], xn[2], 0.f, 0.f, 0.f, 0.f, 0.f};
         load_x(blk + nwv, xn);  // the next block's inputs, in flight during this block
-        v4f d1[4];
+        v4u xh, xm, xl;
+        split3(xv, xh, xm, xl);
+        float h[4][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            d1[q] = b1[q];
+            v4f d = mfma32(a1[q], xl, b1[q]);
+            d = mfma32(a1[q], xm, d);
+            d = mfma32(a1[q], xh, d);
 #pragma unroll
-            for (int t = 0; t < 3; ++t) d1[q] = mfma4(a1[q][t], xv[t], d1[q]);
+            for (int r = 0; r < 4; ++r) h[q][r] = gelu(d[r]);
         }
-        float h1[4][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) h1[q][r] = gelu(d1[q][r]);
         v4f d2[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            d2[q] = b2[q];
+        for (int q = 0; q < 4; ++q) d2[q] = b2[q];
 #pragma unroll
-            for (int qi = 0; qi < 4; ++qi)
+        for (int s = 0; s < 2; ++s) {
+            const float hv[8] = {h[2 * s][0],     h[2 * s][1],     h[2 * s][2],     h[2 * s][3],
+                                 h[2 * s + 1][0], h[2 * s + 1][1], h[2 * s + 1][2], h[2 * s + 1][3]};
+            v4u hh, hm, hl;
+            split3(hv, hh, hm, hl);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) d2[q] = mfma4(a2[q][4 * qi + r], h1[qi][r], d2[q]);
+            for (int q = 0; q < 4; ++q) {
+                d2[q] = mfma32(a2[q][s], hl, d2[q]);
+                d2[q] = mfma32(a2[q][s], hm, d2[q]);
+                d2[q] = mfma32(a2[q][s], hh, d2[q]);
+            }
         }
-        // four independent accumulation chains (one per input tile), summed at the end
-        v4f d3q[4];
+        v4f d3 = b3;
 #pragma unroll
-        for (int qi = 0; qi < 4; ++qi) {
-            d3q[qi] = qi == 0 ? b3 : v4f{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < 2; ++s) {
+            float gv[8];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) d3q[qi] = mfma4(a3[4 * qi + r], gelu(d2[qi][r]), d3q[qi]);
+            for (int j = 0; j < 8; ++j) gv[j] = gelu(d2[2 * s + (j >> 2)][j & 3]);
+            d3 = mfma32x3(a3[s], gv, d3);
         }
-        const v4f d3 = (d3q[0] + d3q[1]) + (d3q[2] + d3q[3]);
         const long p = blk * 16 + c;
         if (p < M) {
 #pragma unroll
@@ -159,7 +227,8 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
 
 // ---- loss and backward on the matrix cores -----------------------------------------------------------
 // One wavefront walks 16-point blocks as the forward does, and per block:
-//   the forward of k_mlp_fwd, keeping gelu'(a1) and gelu'(a2) beside h1 and h2;
+//   the forward, on the FP32 instruction (outputs in k_mlp_fwd's accumulator layout),
+//   keeping gelu'(a1) and gelu'(a2) beside h1 and h2;
 //   dy = 2 (y - t / out_scale) / (6 M) with loss += (y - t / out_scale)^2, or the given dy;
 //   da2 = (W3^T dy) gelu'(a2) and da1 = (W2^T da2) gelu'(a1), products in the forward's
 //   layout (the transposed weights are per-lane A operands too);
