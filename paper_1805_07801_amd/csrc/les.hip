@@ -168,22 +168,25 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
     const long nblk = (M + 15) / 16;
     const long wv = (long)blockIdx.x * (MB / 64) + (threadIdx.x >> 6);
     const long nwv = (long)gridDim.x * (MB / 64);
-    auto load_x = [&](long blk, float (&xv)[3]) {
+    // inputs of a block, loaded from clamped addresses without a branch (M >= 1) so that the
+    // loads stay in flight until layer1 uses them; values past the end are zeroed there
+    auto load_x = [&](long blk, float (&xr)[3]) {
         const long p = blk * 16 + c;
+        const long pc = p < M ? p : M - 1;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int f = 3 * kk + j;
-            xv[j] = (blk < nblk && p < M && f < 9) ? x9[f * M + p] * in_inv : 0.f;
+            xr[j] = x9[(f < 9 ? f : 8) * M + pc];
         }
     };
-    float xn[3];
-    load_x(wv, xn);
-    for (long blk = wv; blk < nblk; blk += nwv) {
-        const float xv[8] = {xn[0], xn[1], xn[2], 0.f, 0.f, 0.f, 0.f, 0.f};
-        load_x(blk + nwv, xn);  // the next block's inputs, in flight during this block
+    // layer 1 of a block: h[q][r] = gelu(a1 x + b1), outputs 16 q + 4 kk + r
+    auto layer1 = [&](long blk, const float (&xr)[3], float (&h)[4][4]) {
+        const bool inb = blk * 16 + c < M;
+        float xv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xv[j] = (inb && 3 * kk + j < 9) ? xr[j] * in_inv : 0.f;
         v4u xh, xm, xl;
         split3(xv, xh, xm, xl);
-        float h[4][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             v4f d = mfma32(a1[q], xl, b1[q]);
@@ -192,6 +195,14 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
 #pragma unroll
             for (int r = 0; r < 4; ++r) h[q][r] = gelu(d[r]);
         }
+    };
+    // software pipeline: layer 1 of the wavefront's next block runs while this block's
+    // layer 2 is on the matrix cores, and the loads run two blocks ahead
+    float xn[3], h[4][4];
+    load_x(wv, xn);
+    layer1(wv, xn, h);
+    load_x(wv + nwv, xn);
+    for (long blk = wv; blk < nblk; blk += nwv) {
         v4f d2[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) d2[q] = b2[q];
@@ -208,6 +219,10 @@ __global__ __launch_bounds__(MB) void k_mlp_fwd(const uint16_t *__restrict__ wb,
                 d2[q] = mfma32(a2[q][s], hh, d2[q]);
             }
         }
+        // the next block's layer 1 (inputs zero past the last block; nothing of it is stored)
+        const float xc[3] = {xn[0], xn[1], xn[2]};
+        load_x(blk + 2 * nwv, xn);
+        layer1(blk + nwv, xc, h);
         v4f d3 = b3;
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -697,6 +712,7 @@ static tk_status mlp_check(const tk_mlp *w) {
 }
 
 tk_status mlp_forward_run(const tk_mlp *w, const float *x9, float *y6, long M, hipStream_t s) {
+    if (M <= 0) return TK_OK;  // the kernel's clamped loads need one point
     // as many workgroups as are resident (each wavefront walks 16-point blocks), no more
     // than there are blocks
     const long nblk = (M + 15) / 16;
