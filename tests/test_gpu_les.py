@@ -144,6 +144,41 @@ def test_les_step_vs_oracle_and_fallback(tk):
     assert fb == 2 and torch.equal(ud2, ub)
 
 
+def test_les_steps_in_separate_calls(tk):
+    """Three calls of one LES step, with other GPU work and synchronisations between them,
+    match the oracle after every step and give the bits of one call of three steps on
+    another state buffer; a closure with another output scale steps to its own oracle
+    result."""
+    import torch
+    n = 32
+    nu, h = 5e-3, 0.004
+    u0 = oinit.random_solenoidal(synth.gaussian_field((3, n, n, n), 11))
+    th = theta0(6, scale=0.3)
+    s_in, s_out = 3.0, 0.05
+    net = tk.Closure(th, in_scale=s_in, out_scale=s_out)
+    s = tk.NS(n, dtype=torch.float32, nu=nu)
+    ua = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    ref = u0
+    t = 0.0
+    for k in range(3):
+        t, fb = tk.les_step(s, net, ua, h, 1, t)
+        assert fb == 0 and abs(t - (k + 1) * h) < 1e-14
+        junk = torch.randn(1 << 20, device="cuda")
+        assert torch.isfinite(junk.sum()).item()
+        torch.cuda.synchronize()
+        ref = ons.ifrk2_step(ref, nu, h, rhs_fn=lambda v: oles.les_rhs(v, th, s_in, s_out))[0]
+        assert diag.rel_l2(ua.cpu().numpy(), ref, n) <= 1e-4, k
+    ub = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    tk.les_step(s, net, ub, h, 3)
+    assert torch.equal(ua, ub)
+    # another output scale
+    net2 = tk.Closure(th, in_scale=s_in, out_scale=2 * s_out)
+    uc = torch.from_numpy(u0.astype(np.complex64)).cuda()
+    tk.les_step(s, net2, uc, h, 1)
+    ref2 = ons.ifrk2_step(u0, nu, h, rhs_fn=lambda v: oles.les_rhs(v, th, s_in, 2 * s_out))[0]
+    assert diag.rel_l2(uc.cpu().numpy(), ref2, n) <= 1e-4
+
+
 PAIRS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 
 
