@@ -39,6 +39,25 @@ def test_forward_vs_oracle(tk, M):
     assert rel(y, ref) <= 1e-5
 
 
+def test_forward_extreme_inputs_vs_oracle(tk):
+    """Inputs that drive the activations far into both GELU tails (|x| up to ~100, where
+    GELU(x) is x or a tiny negative number), exact zeros and values near the FP32 underflow,
+    at a ragged point count: the forward still matches the oracle's exact-erf GELU."""
+    import torch
+    th = theta0(4)
+    M = 4099
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal((9, M)) * 40.0).astype(np.float32)
+    x[:, :64] = 0.0
+    x[:, 64:128] = (rng.standard_normal((9, 64)) * 1e-30).astype(np.float32)
+    net = tk.Closure(th, in_scale=1.0, out_scale=1.0)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = omlp.forward(th, x.astype(np.float64))
+    assert np.all(np.isfinite(y))
+    assert rel(y, ref) <= 1e-5
+    assert rel(y[:, :128], ref[:, :128]) <= 1e-5
+
+
 # flat parameter groups W1, b1, W2, b2, W3, b3
 GROUPS = [(0, 576), (576, 640), (640, 4736), (4736, 4800), (4800, 5184), (5184, 5190)]
 
