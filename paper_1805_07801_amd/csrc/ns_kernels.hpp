@@ -278,44 +278,69 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
     C wr[E - 1];
     if constexpr (RS > 0) stage_twiddles<T, L, E, 2, RS>(jt, tw, wr);
     auto xform = [&](C(&v)[E]) { line_fft<T, L, E, 1, 2, 0, true, false, RS>(v, d, jt, tw, wr); };
+    // The real-FFT merge and split pair X[k] with X[L - k], k = jt + p TPL: for jt > 0 the
+    // partner sits in the mirror lane TPL - jt, register E - 1 - p, and lane 0 pairs register p
+    // with its own register E - p (register 0 with the Nyquist mode, register E / 2 with
+    // itself).  Both results of a pair come from the same sums, so each lane forms the pairs
+    // of its registers p < E / 2 only: the merge hands the partner's result back through the
+    // shuffle, the split stores it at column L - k.
+    constexpr int H = E / 2;
+    const int src = (tid & 63) - jt + ((TPL - jt) & (TPL - 1));
+    auto shfl2 = [&](const C &x) {
+        if constexpr (TPL > 1) {
+            C q;
+            q.x = __shfl(x.x, src, 64);
+            q.y = __shfl(x.y, src, 64);
+            return q;
+        } else {
+            return x;
+        }
+    };
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
-        C v[E], xm[E];
+        C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = nx[i];
         if (f + 1 < NIN) load(nx, f + 1);
-        // X[L - k] from the mirror lane (X[L] itself is a masked mode: zero).  Register r
-        // holds X[jt + r TPL]; it is zero on every lane when r TPL >= KZC0, so register i
-        // of the merge has X[k] = 0 when i is such a register, and X[L - k] = 0 when its
-        // mirror E - 1 - i is one (for lane 0, whose mirror register is E - i, as well;
-        // lane 0's register 0 is the k = 0 case, which takes no mirror).  Those terms are
-        // left out at compile time, and so are the shuffles that would fetch zeros.
-        mirror<T, L, E>(v, xm, jt);
+        // c2r merge.  Register r holds X[jt + r TPL], zero on every lane when r TPL >= KZC0:
+        // a pair whose own or partner register is such a register leaves those terms out at
+        // compile time, and the shuffle that would fetch the zero with them.  X[L] (the
+        // partner of lane 0's register 0) is a masked mode, and X[0] counts with its real part.
+        // Pairs from the last to the first: pair p writes its own register p and register
+        // E - 1 - p, which takes the mirror lane's partner result (lane 0: its own result of
+        // pair p + 1, formed one step before; for p = E/2 - 1 its self-paired register E/2,
+        // 2 X[L/2]).  No register is read after it is written, in any lane.
+        const C xh = v[H];
+        C hnext = mk<T>(0, 0);
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const bool xk_zero = i * TPL >= KZC0;
-            const bool xc_zero = (E - 1 - i) * TPL >= KZC0;
-            // k = jt + i TPL is 0 only in register 0 of lane 0 of the line
-            const bool k0 = i == 0 && jt == 0;
-            C xk = v[i];
-            C xc = cconj(xm[i]);
-            if (i == 0) {
-                xc = k0 ? mk<T>(0, 0) : xc;
-                xk.y = k0 ? (T)0 : xk.y;
-            }
-            C a, d;
-            if (xk_zero) {
-                a = xc;
-                d = mk<T>(-xc.x, -xc.y);
-            } else if (xc_zero) {
+        for (int p = H - 1; p >= 0; --p) {
+            const bool xk_zero = p * TPL >= KZC0;
+            const bool xc_zero = (E - 1 - p) * TPL >= KZC0;  // lane 0's partner E - p as well
+            C xk = v[p];
+            if (p == 0) xk.y = jt == 0 ? (T)0 : xk.y;
+            C a, dd;
+            if (xc_zero) {
                 a = xk;
-                d = xk;
+                dd = xk;
             } else {
-                a = cadd(xk, xc);
-                d = csub(xk, xc);
+                const C s = shfl2(v[E - 1 - p]);
+                const C xp = jt != 0 ? s : (p == 0 ? mk<T>(0, 0) : v[(E - p) % E]);
+                const C xc = cconj(xp);
+                if (xk_zero) {
+                    a = xc;
+                    dd = mk<T>(-xc.x, -xc.y);
+                } else {
+                    a = cadd(xk, xc);
+                    dd = csub(xk, xc);
+                }
             }
-            const C b = cmul(cconj(split_tw(i)), d);
-            v[i] = mk<T>(a.x - b.y, -(a.y + b.x));
+            const C b = cmul(cconj(split_tw(p)), dd);
+            const C hi = mk<T>(a.x + b.y, a.y - b.x);  // conj Z'[L - k]
+            v[p] = mk<T>(a.x - b.y, -(a.y + b.x));     // conj Z'[k]
+            const C m = shfl2(hi);
+            const C own = p == H - 1 ? mk<T>(2 * xh.x, 2 * xh.y) : hnext;
+            v[E - 1 - p] = jt != 0 ? m : own;
+            hnext = hi;
         }
         xform(v);
 #pragma unroll
@@ -347,28 +372,33 @@ __device__ __forceinline__ void ns_p3_tile(V2<T> *w6, long nlines, int KZC, long
             }
         }
     }
-    // forward r2c of the products (unscaled; P5 applies 1/N^3)
+    // forward r2c of the products (unscaled; P5 applies 1/N^3), kz < KZP (whole transit rows:
+    // the padding values are never used); the pairs as in the merge
 #pragma unroll
     for (int f = 0; f < NOUT; ++f) {
         C v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = c[f][i];
         xform(v);
-        C zm[E];
-        mirror<T, L, E>(v, zm, jt);
-        if (valid) {
-            C *o = w6 + f * FS + l * KZP;
+        C *o = w6 + f * FS + l * KZP;
+        const C zh = v[H];
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int k = jt + i * TPL;
-                if (k < KZP) {  // whole transit rows (the padding values are never used)
-                    const C zk = v[i];
-                    const C zc = cconj(zm[i]);
-                    const C a = cadd(zk, zc);
-                    const C b = cmul(split_tw(i), csub(zk, zc));
-                    o[k] = mk<T>((T)0.5 * (a.x + b.y), (T)0.5 * (a.y - b.x));
-                }
+        for (int p = 0; p < H; ++p) {
+            const C s = shfl2(v[E - 1 - p]);
+            const C zc = cconj(jt != 0 ? s : v[(E - p) % E]);  // Z[L - k] (lane 0, p = 0: Z[0])
+            const C a = cadd(v[p], zc);
+            const C b = cmul(split_tw(p), csub(v[p], zc));
+            const int k = jt + p * TPL;
+            if (valid) {
+                if (k < KZP) o[k] = mk<T>((T)0.5 * (a.x + b.y), (T)0.5 * (a.y - b.x));  // X[k]
+                // X[L - k]: column L - k >= (E - 1 - p) TPL + 1, stored only where it can be kept
+                if ((E - 1 - p) * TPL + 1 < KZP && (jt != 0 || p != 0) && L - k < KZP)
+                    o[L - k] = mk<T>((T)0.5 * (a.x - b.y), (T)-0.5 * (a.y + b.x));
             }
+        }
+        if (valid) {
+            // lane 0's register H pairs with itself: X[L/2] = conj Z[L/2]
+            if (jt == 0 && L / 2 < KZP) o[L / 2] = cconj(zh);
         }
     }
     if (umax || part) {
