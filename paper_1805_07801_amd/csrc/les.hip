@@ -66,8 +66,9 @@ __device__ __forceinline__ void load_weights(float *w, const uint16_t *__restric
 // Forward on the matrix cores.  Each layer is a product D = W H of the weights (outputs x
 // inputs) and the activations (inputs x points), taken 16 points at a time by one
 // wavefront with v_mfma_f32_16x16x32_bf16.  The weights are BF16 parameters already; each
-// FP32 activation is split exactly into three BF16 terms, h = hi + mid + lo (split3), so
-// every product w h_i is exact in FP32 and the sums run in FP32 on the FP32 accumulators:
+// FP32 activation is split into three BF16 terms, h = hi + mid + lo (split3: exact for
+// |h| >= 2^-110), so every product w h_i is exact in FP32 and the sums run in FP32 on the
+// FP32 accumulators:
 // the FP32 arithmetic of the definition, in another order, at a quarter of the matrix
 // cycles of the FP32 instruction.  Operand layouts on a wavefront, lane l = 16 kk + c
 // (kk < 4, c < 16):
@@ -96,9 +97,10 @@ __device__ __forceinline__ v4f mfma32(v4u a, v4u b, v4f c) {
 __device__ __forceinline__ unsigned pack_hi16(unsigned lo_elem, unsigned hi_elem) {
     return (lo_elem >> 16) | (hi_elem & 0xffff0000u);
 }
-// v[j] = hi[j] + mid[j] + lo[j] exactly: truncating an FP32 value to its BF16 head leaves a
-// remainder of at most 16 significant bits, and truncating that one leaves at most 8, which
-// BF16 holds exactly.
+// v[j] = hi[j] + mid[j] + lo[j]: truncating an FP32 value to its BF16 head leaves a remainder
+// of at most 16 significant bits, and truncating that one leaves at most 8, which BF16 holds
+// exactly while the remainders are normal numbers (|v| >= 2^-110); below that the third
+// term drops less than 2^-133.
 __device__ __forceinline__ void split3(const float (&v)[8], v4u &hi, v4u &mid, v4u &lo) {
     unsigned uh[8], um[8], ul[8];
 #pragma unroll
